@@ -1,0 +1,176 @@
+/*
+ * corr.h -- C ABI of libcorr, the MI355X (gfx950) correlation hot path for
+ * focus+context correlation views of 3D ensembles (arXiv 2309.03308).
+ *
+ * What it computes (Sec. 3): an ensemble of M members (the paper's E) on an
+ * nx x ny x nz grid; for grid points pA and pB the point-to-point correlation
+ * across members is either the Pearson coefficient (PPMCC, Sec. 3.2) or the
+ * Kraskov k-nearest-neighbour mutual-information estimate (KSG/"KMI",
+ * Sec. 3.2); the indicator of a region (brick) pair is the maximum of these
+ * over pA in A and pB in B (Sec. 3). Batched Bayesian optimal sampling of
+ * that maximum (Sec. 3.1) is declared in bos.h.
+ *
+ * Conventions for every call:
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees caller memory. Library objects (corr_ctx) own their
+ *    internal workspaces.
+ *  - Struct arguments (corr_field, corr_region) are read during the call only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = legacy default
+ *    stream) and the call returns; calls that write HOST outputs synchronise
+ *    that stream before returning.
+ *  - Arguments are validated on the host before anything is enqueued:
+ *    CORR_EINVAL for bad arguments (null pointers, M < 2, k outside
+ *    [1, M-1], regions outside the grid, n < 0, fields of different M),
+ *    CORR_EUNSUPPORTED for a dtype / precision / size this build does not
+ *    handle, CORR_ENOMEM when a workspace cannot be allocated, CORR_EHIP for
+ *    a failed HIP call (its message is kept in corr_last_error()).
+ *    No C++ exception crosses this ABI.
+ *  - One host thread at a time per corr_ctx.
+ *  - Point indices are global linear indices p = x + nx * (y + ny * z),
+ *    int32. A region's local index follows the same x-fastest rule relative
+ *    to its origin.
+ */
+#ifndef CORR_H
+#define CORR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t (same underlying type). */
+typedef struct ihipStream_t* corr_stream_t;
+
+enum corr_status {
+    CORR_OK = 0,
+    CORR_EINVAL = 1,
+    CORR_EUNSUPPORTED = 2,
+    CORR_ENOMEM = 3,
+    CORR_EHIP = 4,
+    CORR_ESTATE = 5
+};
+
+/* Storage type of a field in HBM. FP16 values are upcast exactly to FP32. */
+enum corr_dtype { CORR_F32 = 0, CORR_F16 = 1 };
+
+/* Arithmetic of the Pearson contraction. F32: FP32 operands. F16/BF16: one
+ * pass with 16-bit operands and FP32 accumulation. F16X3/BF16X3: operands
+ * split into hi + lo 16-bit parts, r = hi.hi + hi.lo + lo.hi, FP32
+ * accumulation. */
+enum corr_prec {
+    CORR_PREC_F32 = 0,
+    CORR_PREC_F16 = 1,
+    CORR_PREC_BF16 = 2,
+    CORR_PREC_F16X3 = 3,
+    CORR_PREC_BF16X3 = 4
+};
+
+enum corr_measure { CORR_PEARSON = 0, CORR_KSG = 1 };
+
+/* corr_ksg_mi_pairs flag: use the stored values as the KSG samples instead
+ * of z-scoring each point first. */
+#define CORR_KSG_RAW 1u
+
+typedef struct corr_ctx corr_ctx;
+
+/* An ensemble field (Sec. 3): value(m, p) = data[m * member_stride + p],
+ * member-major. member_stride = 0 means nx * ny * nz. */
+typedef struct corr_field {
+    const void* data;      /* device pointer */
+    int32_t dtype;         /* enum corr_dtype */
+    int32_t M;             /* ensemble members, >= 2 */
+    int32_t nx, ny, nz;    /* grid extent */
+    int64_t member_stride; /* elements between consecutive members */
+} corr_field;
+
+/* A region (the paper's brick): half-open box of grid cells. */
+typedef struct corr_region {
+    int32_t x0, y0, z0;
+    int32_t dx, dy, dz;
+} corr_region;
+
+/* Result of a region-pair maximum. value = max |r| (Pearson) or max MI
+ * (KSG); signed_value = r (or MI) at the argmax; pa, pb = global indices
+ * of the argmax (-1 if nothing was evaluated); n_evaluated = pairs counted. */
+typedef struct corr_max {
+    float value;
+    float signed_value;
+    int32_t pa, pb;
+    int64_t n_evaluated;
+} corr_max;
+
+/* Library version string. */
+const char* corr_version(void);
+
+/* Create a context on HIP device `device`; allocates the digamma table and
+ * small device scratch. *out receives the context. */
+int corr_create(int device, corr_ctx** out);
+
+/* Wait for the context's work, free its workspaces and the context. NULL ok. */
+void corr_destroy(corr_ctx* ctx);
+
+/* Static description of a status code. */
+const char* corr_status_str(int status);
+
+/* Last error message of the calling thread ("" if none). */
+const char* corr_last_error(void);
+
+/*
+ * Per-point statistics of every grid point of field A (Sec. 3.2: Pearson
+ * needs only means and variances; KSG works on z-scored samples).
+ * Two-pass sums in member order in FP64. Outputs (device, nx*ny*nz floats
+ * each, any may be NULL): mu32 = fl32(mean), inv32 = fl32(1 / sigma_pop)
+ * (0 for a constant point), sigma = fl32(sigma_pop) (the ensemble spread).
+ */
+int corr_standardize(corr_ctx* ctx, const corr_field* A, float* mu32, float* inv32, float* sigma,
+                     corr_stream_t stream);
+
+/*
+ * Pearson r for a list of point pairs (Sec. 3.2):
+ *   r_i = sum_m (a_m - mean a)(b_m - mean b) / sqrt(sum (a - mean a)^2 sum (b - mean b)^2)
+ * with a = A[:, pairs[i][0]], b = B[:, pairs[i][1]], clamped to [-1, 1];
+ * a constant point gives r = 0.
+ * pairs: device int32 [n][2] of global indices into A and B.
+ * r_out: device float [n]. prec: enum corr_prec.
+ */
+int corr_pearson_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs,
+                       int64_t n, int prec, float* r_out, corr_stream_t stream);
+
+/*
+ * Kraskov (KSG) mutual information, in nats, for a list of point pairs
+ * (Sec. 3.2). For pair (a, b): x_i, y_i are the z-scored samples of a and b
+ * (z = fl32(fl32(v - mu32) * inv32), see corr_standardize; raw values with
+ * CORR_KSG_RAW); d_ij = max(|x_i - x_j|, |y_i - y_j|) in FP32; eps_i = k-th
+ * smallest d_ij over j != i; n_x,i = #{j != i : |x_i - x_j| < eps_i}, n_y,i
+ * alike; MI = psi(M) + psi(k) - (1/M) sum_i [psi(n_x,i + 1) + psi(n_y,i + 1)].
+ * A constant point gives MI = 0 and zero counts (not with CORR_KSG_RAW).
+ * pairs: device int32 [n][2]; mi_out: device float [n];
+ * counts_out: NULL or device int32 [n][M][2] receiving (n_x,i, n_y,i).
+ * k in [1, min(M-1, 31)].
+ */
+int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs,
+                      int64_t n, int32_t k, uint32_t flags, float* mi_out, int32_t* counts_out,
+                      corr_stream_t stream);
+
+/*
+ * Region-pair maximum (Sec. 3: the brick-pair indicator is the maximum of
+ * the point-to-point correlations between the two bricks).
+ *  measure CORR_PEARSON: objective |r|; CORR_KSG: objective MI.
+ *  sample_pairs == NULL: every (pA, pB) in ra x rb is evaluated (for Pearson
+ *    as one fused MFMA contraction that never stores the correlations);
+ *  otherwise: device int32 [n_samples][2] of global indices, each inside
+ *    ra resp. rb, and only those pairs are evaluated.
+ * When A and B are the same field, pA == pB is skipped. Ties go to the
+ * smallest (local pA, local pB) for exhaustive runs. prec applies to
+ * Pearson; k to KSG. out: HOST pointer; the call synchronises `stream`.
+ */
+int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                    const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                    int64_t n_samples, corr_max* out, corr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORR_H */

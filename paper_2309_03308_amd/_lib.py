@@ -1,0 +1,82 @@
+"""ctypes binding of libcorr (see include/corr.h and include/bos.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.
+There is no fallback: if libcorr.so is missing or a call fails, an exception
+is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcorr.so")
+
+CORR_OK, CORR_EINVAL, CORR_EUNSUPPORTED, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = range(6)
+CORR_F32, CORR_F16 = 0, 1
+PREC = {"f32": 0, "f16": 1, "bf16": 2, "f16x3": 3, "bf16x3": 4}
+MEASURE = {"pearson": 0, "ksg": 1}
+CORR_KSG_RAW = 1
+
+
+class corr_field(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("member_stride", ctypes.c_int64)]
+
+
+class corr_region(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_int32), ("y0", ctypes.c_int32), ("z0", ctypes.c_int32),
+                ("dx", ctypes.c_int32), ("dy", ctypes.c_int32), ("dz", ctypes.c_int32)]
+
+
+class corr_max(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_float), ("signed_value", ctypes.c_float), ("pa", ctypes.c_int32),
+                ("pb", ctypes.c_int32), ("n_evaluated", ctypes.c_int64)]
+
+
+class CorrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libcorr status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# (name, restype, argtypes) for every exported entry point
+_P, _I, _I32, _I64, _U32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+SIGNATURES = {
+    "corr_version": (ctypes.c_char_p, []),
+    "corr_create": (_I, [_I, ctypes.POINTER(_P)]),
+    "corr_destroy": (None, [_P]),
+    "corr_status_str": (ctypes.c_char_p, [_I]),
+    "corr_last_error": (ctypes.c_char_p, []),
+    "corr_standardize": (_I, [_P, ctypes.POINTER(corr_field), _P, _P, _P, _P]),
+    "corr_pearson_pairs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I64, _I, _P, _P]),
+    "corr_ksg_mi_pairs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I64, _I32, _U32,
+                               _P, _P, _P]),
+    "corr_region_max": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), ctypes.POINTER(corr_field),
+                             ctypes.POINTER(corr_region), _I, _I, _I32, _P, _I64, ctypes.POINTER(corr_max), _P]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libcorr.so and declare the signatures; raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libcorr.so not built ({path}); run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != CORR_OK:
+        L = load()
+        raise CorrError(status, L.corr_last_error().decode())

@@ -1,0 +1,458 @@
+// Host side of the C ABI: validation, contexts, workspaces, dispatch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace corr {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out) {
+    if (bytes == 0) bytes = 256;
+    if (ctx->ws_size[slot] < bytes) {
+        if (ctx->ws[slot]) {
+            CORR_HIP(hipStreamSynchronize(stream));
+            CORR_HIP(hipFree(ctx->ws[slot]));
+            ctx->ws[slot] = nullptr;
+            ctx->ws_size[slot] = 0;
+        }
+        size_t want = bytes + bytes / 8;
+        hipError_t e = hipMalloc(&ctx->ws[slot], want);
+        if (e != hipSuccess) {
+            ctx->ws[slot] = nullptr;
+            (void)hipGetLastError();
+            return fail(CORR_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+        }
+        ctx->ws_size[slot] = want;
+    }
+    *out = ctx->ws[slot];
+    return CORR_OK;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+    fill_u64_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(p, n, v);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+__global__ void self_col_kernel(Box a, Box b, int32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.count()) out[i] = (int32_t)b.local(a.global(i));
+}
+
+int gemm_row_pad();
+int gemm_col_pad();
+int gemm_k_pad(int prec);
+
+// ---- validation -------------------------------------------------------------
+static int64_t field_points(const corr_field& f) { return (int64_t)f.nx * f.ny * f.nz; }
+
+static int check_field(const corr_field* f, const char* name) {
+    if (!f) return fail(CORR_EINVAL, std::string(name) + ": null field");
+    if (!f->data) return fail(CORR_EINVAL, std::string(name) + ": null data pointer");
+    if (f->dtype != CORR_F32 && f->dtype != CORR_F16)
+        return fail(CORR_EUNSUPPORTED, std::string(name) + ": unsupported dtype");
+    if (f->M < 2) return fail(CORR_EINVAL, std::string(name) + ": M must be >= 2");
+    if (f->nx < 1 || f->ny < 1 || f->nz < 1) return fail(CORR_EINVAL, std::string(name) + ": empty grid");
+    if (field_points(*f) >= (int64_t(1) << 31))
+        return fail(CORR_EUNSUPPORTED, std::string(name) + ": more than 2^31-1 grid points");
+    if (f->member_stride != 0 && f->member_stride < field_points(*f))
+        return fail(CORR_EINVAL, std::string(name) + ": member_stride smaller than the grid");
+    return CORR_OK;
+}
+
+static int check_region(const corr_region* r, const corr_field& f, const char* name) {
+    if (!r) return fail(CORR_EINVAL, std::string(name) + ": null region");
+    if (r->dx < 1 || r->dy < 1 || r->dz < 1) return fail(CORR_EINVAL, std::string(name) + ": empty region");
+    if (r->x0 < 0 || r->y0 < 0 || r->z0 < 0 || r->x0 + r->dx > f.nx || r->y0 + r->dy > f.ny ||
+        r->z0 + r->dz > f.nz)
+        return fail(CORR_EINVAL, std::string(name) + ": region outside the grid");
+    return CORR_OK;
+}
+
+static bool same_field(const corr_field& a, const corr_field& b) {
+    int64_t sa = a.member_stride ? a.member_stride : field_points(a);
+    int64_t sb = b.member_stride ? b.member_stride : field_points(b);
+    return a.data == b.data && a.dtype == b.dtype && a.M == b.M && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz &&
+           sa == sb;
+}
+
+static Box whole_box(const corr_field& f) { return Box{0, 0, 0, f.nx, f.ny, f.nz, f.nx, f.ny}; }
+static Box region_box(const corr_region& r, const corr_field& f) {
+    return Box{r.x0, r.y0, r.z0, r.dx, r.dy, r.dz, f.nx, f.ny};
+}
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+static bool boxes_overlap(const Box& a, const Box& b) {
+    return a.x0 < b.x0 + b.dx && b.x0 < a.x0 + a.dx && a.y0 < b.y0 + b.dy && b.y0 < a.y0 + a.dy &&
+           a.z0 < b.z0 + b.dz && b.z0 < a.z0 + a.dz;
+}
+static int64_t overlap_count(const Box& a, const Box& b) {
+    if (!boxes_overlap(a, b)) return 0;
+    int64_t ox = std::min(a.x0 + a.dx, b.x0 + b.dx) - std::max(a.x0, b.x0);
+    int64_t oy = std::min(a.y0 + a.dy, b.y0 + b.dy) - std::max(a.y0, b.y0);
+    int64_t oz = std::min(a.z0 + a.dz, b.z0 + b.dz) - std::max(a.z0, b.z0);
+    return ox * oy * oz;
+}
+
+// Statistics accumulate in FP64 for KSG (its integer counts must be exactly
+// reproducible) and for large ensembles (cancellation); FP32 otherwise.
+static bool stats_acc64(int measure, int M) { return measure == CORR_KSG || M > 256; }
+
+// Standardise the points of `box` into (stats slot, hi slot, lo slot).
+static int standardize_box(corr_ctx* ctx, const corr_field& f, const Box& box, bool acc64, int fmt, int64_t rows_pad,
+                           int64_t ld, int stats_slot, int hi_slot, int lo_slot, hipStream_t s, Stats* st_out,
+                           void** hi, void** lo) {
+    const int64_t n = box.count();
+    void* sb = nullptr;
+    int rc = ws_get(ctx, stats_slot, sizeof(float) * 4 * (size_t)n, s, &sb);
+    if (rc) return rc;
+    Stats st = stats_view((float*)sb, n);
+    if (fmt != ZF_RAW) {
+        rc = launch_stats(f, box, acc64, st, s);
+        if (rc) return rc;
+    }
+    size_t es = (fmt == ZF_KSG || fmt == ZF_RAW || fmt == ZF_F32) ? 4 : 2;
+    rc = ws_get(ctx, hi_slot, es * (size_t)(rows_pad * ld), s, hi);
+    if (rc) return rc;
+    *lo = nullptr;
+    if (fmt == ZF_F16X2 || fmt == ZF_BF16X2) {
+        rc = ws_get(ctx, lo_slot, es * (size_t)(rows_pad * ld), s, lo);
+        if (rc) return rc;
+    }
+    rc = launch_transpose(f, box, st, fmt, *hi, *lo, rows_pad, ld, s);
+    if (rc) return rc;
+    if (st_out) *st_out = st;
+    return CORR_OK;
+}
+
+static int read_keys(corr_ctx* ctx, hipStream_t s, unsigned long long* k0, unsigned long long* k1) {
+    CORR_HIP(hipMemcpyAsync(ctx->keys_host, ctx->keys, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    CORR_HIP(hipStreamSynchronize(s));
+    *k0 = ctx->keys_host[0];
+    *k1 = ctx->keys_host[1];
+    return CORR_OK;
+}
+
+static void decode_key(unsigned long long key, const Box& ba, const Box& bb, bool is_abs, corr_max* out) {
+    if (key == 0) {
+        out->value = 0.0f;
+        out->signed_value = 0.0f;
+        out->pa = out->pb = -1;
+        return;
+    }
+    float v = from_order_bits((uint32_t)(key >> 32));
+    uint32_t lin = key_lin(key);
+    int64_t nb = bb.count();
+    int64_t la = lin / nb, lb = lin % nb;
+    out->value = v;
+    out->signed_value = (is_abs && (key & 1ull)) ? -v : v;
+    out->pa = ba.global(la);
+    out->pb = bb.global(lb);
+}
+
+}  // namespace corr
+
+using namespace corr;
+
+extern "C" {
+
+const char* corr_version(void) { return "libcorr 0.1 (gfx950)"; }
+
+const char* corr_status_str(int status) {
+    switch (status) {
+        case CORR_OK: return "ok";
+        case CORR_EINVAL: return "invalid argument";
+        case CORR_EUNSUPPORTED: return "unsupported";
+        case CORR_ENOMEM: return "out of memory";
+        case CORR_EHIP: return "HIP error";
+        case CORR_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* corr_last_error(void) { return g_last_error.c_str(); }
+
+int corr_create(int device, corr_ctx** out) {
+    if (!out) return fail(CORR_EINVAL, "corr_create: null out");
+    *out = nullptr;
+    int ndev = 0;
+    CORR_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(CORR_EINVAL, "corr_create: no such device");
+    CORR_HIP(hipSetDevice(device));
+    corr_ctx* c = new (std::nothrow) corr_ctx();
+    if (!c) return fail(CORR_ENOMEM, "corr_create: host allocation failed");
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+    // digamma at integers (the log-derivative of Gamma): psi(1) = -gamma,
+    // psi(n + 1) = psi(n) + 1/n.
+    c->psi_max = 4100;
+    double* h = new double[c->psi_max + 1];
+    h[0] = 0.0;
+    h[1] = -0.57721566490153286060651209008240243;
+    for (int n = 1; n < c->psi_max; ++n) h[n + 1] = h[n] + 1.0 / (double)n;
+    hipError_t e = hipMalloc(&c->psi, sizeof(double) * (c->psi_max + 1));
+    if (e == hipSuccess) e = hipMemcpy(c->psi, h, sizeof(double) * (c->psi_max + 1), hipMemcpyHostToDevice);
+    delete[] h;
+    if (e == hipSuccess) e = hipMalloc(&c->keys, 64 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipHostMalloc(&c->keys_host, 64 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        corr_destroy(c);
+        return fail(CORR_EHIP, std::string("corr_create: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return CORR_OK;
+}
+
+void corr_destroy(corr_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < WS_COUNT; ++i)
+        if (c->ws[i]) (void)hipFree(c->ws[i]);
+    if (c->psi) (void)hipFree(c->psi);
+    if (c->keys) (void)hipFree(c->keys);
+    if (c->keys_host) (void)hipHostFree(c->keys_host);
+    delete c;
+}
+
+int corr_standardize(corr_ctx* ctx, const corr_field* A, float* mu32, float* inv32, float* sigma,
+                     corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Box box = whole_box(*A);
+    const int64_t n = box.count();
+    void* sb = nullptr;
+    rc = ws_get(ctx, WS_STATS_A, sizeof(float) * 4 * (size_t)n, s, &sb);
+    if (rc) return rc;
+    Stats st = stats_view((float*)sb, n);
+    rc = launch_stats(*A, box, true, st, s);
+    if (rc) return rc;
+    if (mu32) CORR_HIP(hipMemcpyAsync(mu32, st.mu32, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    if (inv32) CORR_HIP(hipMemcpyAsync(inv32, st.inv32, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    if (sigma) CORR_HIP(hipMemcpyAsync(sigma, st.sigma, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    return CORR_OK;
+}
+
+int corr_pearson_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
+                       int prec, float* r_out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if (n < 0) return fail(CORR_EINVAL, "n < 0");
+    if (prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3) return fail(CORR_EUNSUPPORTED, "unknown precision");
+    if (n == 0) return CORR_OK;
+    if (!pairs || !r_out) return fail(CORR_EINVAL, "null pairs or output");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t ld = round_up(A->M, 16);
+    const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
+    Box ba = whole_box(*A), bb = whole_box(*B);
+    void *ah, *al, *bh, *bl;
+    rc = standardize_box(ctx, *A, ba, acc64, zfmt_for_prec(prec), ba.count(), ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s,
+                         nullptr, &ah, &al);
+    if (rc) return rc;
+    if (same_field(*A, *B)) {
+        bh = ah;
+        bl = al;
+    } else {
+        rc = standardize_box(ctx, *B, bb, acc64, zfmt_for_prec(prec), bb.count(), ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s,
+                             nullptr, &bh, &bl);
+        if (rc) return rc;
+    }
+    return launch_pearson_pairs(prec, ah, al, bh, bl, ld, pairs, n, r_out, ba, bb, 0, nullptr, s);
+}
+
+int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
+                      int32_t k, uint32_t flags, float* mi_out, int32_t* counts_out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if (n < 0) return fail(CORR_EINVAL, "n < 0");
+    if (k < 1 || k > A->M - 1) return fail(CORR_EINVAL, "k must be in [1, M-1]");
+    if (k > 31) return fail(CORR_EUNSUPPORTED, "k > 31");
+    if (A->M > 2048) return fail(CORR_EUNSUPPORTED, "M > 2048");
+    if (flags & ~CORR_KSG_RAW) return fail(CORR_EINVAL, "unknown flags");
+    if (n == 0) return CORR_OK;
+    if (!pairs || (!mi_out && !counts_out)) return fail(CORR_EINVAL, "null pairs or outputs");
+    hipStream_t s = (hipStream_t)stream;
+    const bool raw = flags & CORR_KSG_RAW;
+    const int fmt = raw ? ZF_RAW : ZF_KSG;
+    const int64_t ld = round_up(A->M, 4);
+    Box ba = whole_box(*A), bb = whole_box(*B);
+    Stats sa{}, sb{};
+    void *za, *zb, *unused;
+    rc = standardize_box(ctx, *A, ba, true, fmt, ba.count(), ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
+    if (rc) return rc;
+    if (same_field(*A, *B)) {
+        zb = za;
+        sb = sa;
+    } else {
+        rc = standardize_box(ctx, *B, bb, true, fmt, bb.count(), ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb,
+                             &unused);
+        if (rc) return rc;
+    }
+    KsgArgs a{};
+    a.za = (const float*)za;
+    a.zb = (const float*)zb;
+    a.ld = ld;
+    a.inv_a = raw ? nullptr : sa.inv32;
+    a.inv_b = raw ? nullptr : sb.inv32;
+    a.pairs = pairs;
+    a.n = n;
+    a.M = A->M;
+    a.k = k;
+    a.psi = ctx->psi;
+    a.mi_out = mi_out;
+    a.counts_out = counts_out;
+    a.key = nullptr;
+    a.ba = ba;
+    a.bb = bb;
+    a.same_field = 0;
+    return launch_ksg(a, ctx->num_cus, s);
+}
+
+int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                    const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                    int64_t n_samples, corr_max* out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (!out) return fail(CORR_EINVAL, "null output");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if ((rc = check_region(ra, *A, "ra"))) return rc;
+    if ((rc = check_region(rb, *B, "rb"))) return rc;
+    if (measure != CORR_PEARSON && measure != CORR_KSG) return fail(CORR_EINVAL, "unknown measure");
+    if (measure == CORR_PEARSON && (prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3))
+        return fail(CORR_EUNSUPPORTED, "unknown precision");
+    if (measure == CORR_KSG) {
+        if (k < 1 || k > A->M - 1) return fail(CORR_EINVAL, "k must be in [1, M-1]");
+        if (k > 31) return fail(CORR_EUNSUPPORTED, "k > 31");
+        if (A->M > 2048) return fail(CORR_EUNSUPPORTED, "M > 2048");
+    }
+    if (n_samples < 0) return fail(CORR_EINVAL, "n_samples < 0");
+    if (sample_pairs == nullptr && n_samples != 0)
+        return fail(CORR_EINVAL, "n_samples given without sample_pairs");
+    hipStream_t s = (hipStream_t)stream;
+    Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
+    const int64_t na = ba.count(), nb = bb.count();
+    if (na * nb >= (int64_t(1) << 31)) return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
+    const bool sf = same_field(*A, *B);
+    memset(out, 0, sizeof(*out));
+    out->pa = out->pb = -1;
+    rc = launch_fill_u64(ctx->keys, 2, 0ull, s);
+    if (rc) return rc;
+    const bool exhaustive = sample_pairs == nullptr;
+    if (!exhaustive && n_samples == 0) return CORR_OK;
+
+    if (measure == CORR_PEARSON) {
+        const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
+        const int fmt = zfmt_for_prec(prec);
+        void *ah, *al, *bh, *bl;
+        if (exhaustive) {
+            const int64_t K = round_up(A->M, gemm_k_pad(prec));
+            const int64_t na_pad = round_up(na, gemm_row_pad()), nb_pad = round_up(nb, gemm_col_pad());
+            rc = standardize_box(ctx, *A, ba, acc64, fmt, na_pad, K, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah,
+                                 &al);
+            if (rc) return rc;
+            rc = standardize_box(ctx, *B, bb, acc64, fmt, nb_pad, K, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh,
+                                 &bl);
+            if (rc) return rc;
+            const int32_t* self_col = nullptr;
+            int64_t n_self = 0;
+            if (sf && boxes_overlap(ba, bb)) {
+                void* m = nullptr;
+                rc = ws_get(ctx, WS_MISC, sizeof(int32_t) * (size_t)na, s, &m);
+                if (rc) return rc;
+                self_col_kernel<<<dim3((unsigned)((na + 255) / 256)), 256, 0, s>>>(ba, bb, (int32_t*)m);
+                CORR_LAUNCH_CHECK();
+                self_col = (const int32_t*)m;
+                n_self = overlap_count(ba, bb);
+            }
+            GemmArgs g{};
+            g.prec = prec;
+            g.a_hi = ah; g.a_lo = al; g.b_hi = bh; g.b_lo = bl;
+            g.K = K;
+            g.na = na; g.nb = nb; g.na_pad = na_pad; g.nb_pad = nb_pad;
+            g.self_col = self_col;
+            g.key = ctx->keys;
+            rc = launch_gemm_max(g, ctx->num_cus, s);
+            if (rc) return rc;
+            unsigned long long k0, k1;
+            if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
+            decode_key(k0, ba, bb, true, out);
+            out->n_evaluated = na * nb - n_self;
+            return CORR_OK;
+        }
+        const int64_t ld = round_up(A->M, 16);
+        rc = standardize_box(ctx, *A, ba, acc64, fmt, na, ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
+        if (rc) return rc;
+        rc = standardize_box(ctx, *B, bb, acc64, fmt, nb, ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
+        if (rc) return rc;
+        rc = launch_pearson_pairs(prec, ah, al, bh, bl, ld, sample_pairs, n_samples, nullptr, ba, bb, sf ? 1 : 0,
+                                  ctx->keys, s);
+        if (rc) return rc;
+        unsigned long long k0, k1;
+        if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
+        decode_key(k0, ba, bb, true, out);
+        out->n_evaluated = (int64_t)k1;
+        return CORR_OK;
+    }
+
+    // KSG
+    const int64_t ld = round_up(A->M, 4);
+    Stats sa{}, sb{};
+    void *za, *zb, *unused;
+    rc = standardize_box(ctx, *A, ba, true, ZF_KSG, na, ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
+    if (rc) return rc;
+    rc = standardize_box(ctx, *B, bb, true, ZF_KSG, nb, ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb, &unused);
+    if (rc) return rc;
+    KsgArgs a{};
+    a.za = (const float*)za;
+    a.zb = (const float*)zb;
+    a.ld = ld;
+    a.inv_a = sa.inv32;
+    a.inv_b = sb.inv32;
+    a.pairs = sample_pairs;
+    a.n = n_samples;
+    a.M = A->M;
+    a.k = k;
+    a.psi = ctx->psi;
+    a.key = ctx->keys;
+    a.ba = ba;
+    a.bb = bb;
+    a.same_field = sf ? 1 : 0;
+    rc = launch_ksg(a, ctx->num_cus, s);
+    if (rc) return rc;
+    unsigned long long k0, k1;
+    if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
+    decode_key(k0, ba, bb, false, out);
+    out->n_evaluated = (int64_t)k1;
+    return CORR_OK;
+}
+
+}  // extern "C"

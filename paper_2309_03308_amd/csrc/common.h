@@ -1,0 +1,171 @@
+// Internal declarations shared by libcorr's translation units (not part of
+// the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/corr.h"
+
+namespace corr {
+
+// ---- error plumbing -------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+
+#define CORR_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::corr::fail(CORR_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CORR_LAUNCH_CHECK() CORR_HIP(hipGetLastError())
+
+// ---- point sets -------------------------------------------------------------
+// A box of grid cells enumerated in local x-fastest order; the whole grid is
+// the box (0,0,0,nx,ny,nz).
+struct Box {
+    int32_t x0, y0, z0, dx, dy, dz;
+    int32_t nx, ny;  // grid extent used for global indexing
+    __host__ __device__ int64_t count() const { return (int64_t)dx * dy * dz; }
+    __host__ __device__ int32_t global(int64_t i) const {
+        int32_t lx = (int32_t)(i % dx);
+        int64_t r = i / dx;
+        int32_t ly = (int32_t)(r % dy);
+        int32_t lz = (int32_t)(r / dy);
+        return (x0 + lx) + nx * ((y0 + ly) + ny * (z0 + lz));
+    }
+    // local index of a global point, or -1 if outside
+    __host__ __device__ int64_t local(int32_t p) const {
+        int32_t x = p % nx, r = p / nx;
+        int32_t y = r % ny, z = r / ny;
+        x -= x0; y -= y0; z -= z0;
+        if (x < 0 || y < 0 || z < 0 || x >= dx || y >= dy || z >= dz) return -1;
+        return x + (int64_t)dx * (y + (int64_t)dy * z);
+    }
+};
+
+// ---- workspace --------------------------------------------------------------
+enum WsSlot {
+    WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
+    WS_PAIRS, WS_MISC, WS_COUNT
+};
+
+}  // namespace corr
+
+struct corr_ctx {
+    int device = 0;
+    int num_cus = 256;
+    double* psi = nullptr;   // device psi(n), n = 0..psi_max (psi[0] unused)
+    int psi_max = 0;
+    void* ws[corr::WS_COUNT] = {};
+    size_t ws_size[corr::WS_COUNT] = {};
+    unsigned long long* keys = nullptr;     // device scratch for max keys
+    unsigned long long* keys_host = nullptr;  // pinned host mirror
+};
+
+namespace corr {
+
+// Grow-only workspace buffer; synchronises `stream` before replacing a buffer.
+int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out);
+
+// ---- statistics layout ------------------------------------------------------
+// Per point of a point set, four float arrays of length n (contiguous):
+// [0] mu32, [1] inv32 = 1/sigma_pop (KSG), [2] rs32 = 1/sqrt(sum sq dev)
+// (Pearson), [3] sigma_pop.
+struct Stats {
+    float* mu32;
+    float* inv32;
+    float* rs32;
+    float* sigma;
+};
+inline Stats stats_view(float* base, int64_t n) { return {base, base + n, base + 2 * n, base + 3 * n}; }
+
+// Launchers (standardize.hip). acc64 selects FP64 accumulation.
+int launch_stats(const corr_field& f, const Box& box, bool acc64, Stats st, hipStream_t s);
+
+// Output formats of the transpose-normalise kernel.
+enum ZFormat { ZF_KSG = 0, ZF_RAW = 1, ZF_F32 = 2, ZF_F16 = 3, ZF_BF16 = 4, ZF_F16X2 = 5, ZF_BF16X2 = 6 };
+// Writes rows[i][m] for i in [0, rows_pad) and m in [0, ld); rows i >= count
+// and members m >= M are zero. hi / lo as required by the format.
+int launch_transpose(const corr_field& f, const Box& box, Stats st, int fmt, void* hi, void* lo,
+                     int64_t rows_pad, int64_t ld, hipStream_t s);
+
+int zfmt_for_prec(int prec);
+bool prec_split(int prec);
+size_t prec_elem_bytes(int prec);
+
+// pairs.hip
+// Rows of za/zb are the local indices of the boxes (a whole-grid box makes
+// them global indices). key (may be NULL) receives the fused max of |r|.
+int launch_pearson_pairs(int prec, const void* za_hi, const void* za_lo, const void* zb_hi, const void* zb_lo,
+                         int64_t ld, const int32_t* pairs, int64_t n, float* r_out, const Box& ba, const Box& bb,
+                         int same_field, unsigned long long* key, hipStream_t s);
+
+// ksg.hip
+struct KsgArgs {
+    const float* za;  // point-major rows, row stride ld
+    const float* zb;
+    int64_t ld;
+    const float* inv_a;  // per-point inv32 of the row sets (NULL: raw mode)
+    const float* inv_b;
+    const int32_t* pairs;  // global indices (NULL: implicit all pairs of the boxes)
+    int64_t n;
+    int M;
+    int k;
+    const double* psi;
+    float* mi_out;         // may be NULL
+    int32_t* counts_out;   // may be NULL
+    unsigned long long* key;  // may be NULL: fused region max
+    Box ba, bb;            // rows of za/zb are the boxes' local indices
+    int same_field;        // skip pA == pB
+};
+int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s);
+
+// gemm.hip
+struct GemmArgs {
+    int prec;
+    const void* a_hi; const void* a_lo;
+    const void* b_hi; const void* b_lo;
+    int64_t K;            // padded reduction length (row stride in elements)
+    int64_t na, nb;       // valid rows
+    int64_t na_pad, nb_pad;
+    const int32_t* self_col;  // per A row: local B column of the same point, or -1 (NULL: none)
+    unsigned long long* key;
+};
+int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s);
+
+// small utility kernels (api.hip)
+int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+
+// Orderable 32-bit image of a float: monotone in the float's value.
+__host__ __device__ inline uint32_t order_bits(float v) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float from_order_bits(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    float v;
+    __builtin_memcpy(&v, &u, 4);
+    return v;
+}
+
+// Max key: [63:32] order_bits(objective), [31:1] 0x7fffffff - lin where lin
+// is the local linear pair index la * nb + lb (< 2^31), [0] sign of the
+// correlation at that pair. The largest key holds the largest objective and,
+// among equal objectives, the smallest lin.
+__host__ __device__ inline unsigned long long make_key(float obj, uint32_t lin, uint32_t neg) {
+    return ((unsigned long long)order_bits(obj) << 32) |
+           ((unsigned long long)((0x7fffffffu - lin) & 0x7fffffffu) << 1) | (unsigned long long)(neg & 1u);
+}
+__host__ __device__ inline uint32_t key_lin(unsigned long long key) {
+    return 0x7fffffffu - (uint32_t)((key >> 1) & 0x7fffffffu);
+}
+
+}  // namespace corr

@@ -1,0 +1,297 @@
+// Exhaustive Pearson region maximum as one MFMA contraction (Sec. 3: the
+// brick-pair indicator is the maximum of all point-to-point correlations
+// between the two bricks).
+//
+// With point-major standardised rows Zhat_A [na][K] and Zhat_B [nb][K]
+// (K = members, zero-padded), R = Zhat_A Zhat_B^T holds every r(pA, pB).
+// R is never stored: each tile's epilogue folds |r| into a running maximum.
+//
+// Design (gfx950):
+//  - workgroup = 4 waves (2 x 2), workgroup tile 128 (A rows) x 256 (B rows),
+//    wave tile 64 x 128 = 2 x 4 blocks of v_mfma_f32_32x32x16_{f16,bf16}
+//    (v_mfma_f32_32x32x2_f32 for FP32 operands), FP32 accumulators;
+//  - K is consumed in chunks staged through LDS, double-buffered (global
+//    loads of chunk c+1 are in flight while chunk c is multiplied); LDS rows
+//    are padded by 16 bytes so the 16-byte operand reads are conflict-free;
+//  - split modes hold hi and lo parts and issue hi.hi + hi.lo + lo.hi;
+//  - persistent workgroups walk tiles in an XCD-grouped order, so the
+//    workgroups resident on one XCD (one L2) work on neighbouring tiles;
+//  - epilogue: per-lane max of |r| (v_max3 with abs modifiers), wave max by
+//    shuffles; only when a tile beats the wave's best so far (rare after the
+//    first tiles) does the wave locate the element, picking the smallest
+//    linear index among equal values. One 64-bit atomicMax per wave at the
+//    end publishes (|r|, index, sign) -- independent of scheduling order.
+#include "common.h"
+
+namespace corr {
+
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+typedef float f16_t __attribute__((ext_vector_type(16)));
+
+constexpr int G_BM = 128, G_BN = 256;  // workgroup tile
+constexpr int G_WM = 2, G_WN = 4;      // 32x32 blocks per wave
+constexpr int G_THREADS = 256;
+
+template <int PREC>
+struct GemmTraits {
+    static constexpr bool F32 = PREC == CORR_PREC_F32;
+    static constexpr bool SPLIT = PREC == CORR_PREC_F16X3 || PREC == CORR_PREC_BF16X3;
+    static constexpr bool BF = PREC == CORR_PREC_BF16 || PREC == CORR_PREC_BF16X3;
+    static constexpr int ES = F32 ? 4 : 2;              // element bytes
+    static constexpr int KC = F32 ? 16 : 32;            // chunk length (elements) = 64 bytes per row
+    static constexpr int ROWB = KC * ES + 16;           // padded LDS row bytes
+    static constexpr int PARTS = SPLIT ? 2 : 1;
+    static constexpr int STAGE = PARTS * (G_BM + G_BN) * ROWB;  // bytes per LDS stage
+};
+
+template <int PREC>
+__device__ __forceinline__ void mfma_step(f16_t& acc, const char* pa, const char* pb, int e) {
+    using T = GemmTraits<PREC>;
+    if constexpr (T::F32) {
+        float a = reinterpret_cast<const float*>(pa)[e];
+        float b = reinterpret_cast<const float*>(pb)[e];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    } else if constexpr (T::BF) {
+        b8_t a = *reinterpret_cast<const b8_t*>(pa);
+        b8_t b = *reinterpret_cast<const b8_t*>(pb);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    } else {
+        h8_t a = *reinterpret_cast<const h8_t*>(pa);
+        h8_t b = *reinterpret_cast<const h8_t*>(pb);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int n_ti, int n_tj) {
+    using T = GemmTraits<PREC>;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;  // wave position in the 2 x 2 grid
+    const int64_t rowb_g = g.K * T::ES;       // global row bytes
+    const int n_chunks = (int)(g.K / T::KC);
+    const int64_t n_tiles = (int64_t)n_ti * n_tj;
+
+    // XCD-grouped logical workgroup id: blocks are dealt round-robin to the
+    // 8 XCDs, so give the blocks of one XCD consecutive logical ids.
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    const int lg = (G % 8 == 0) ? ((b % 8) * (G / 8) + b / 8) : b;
+
+    float best = -1.0f;
+    unsigned long long best_key = 0;
+
+    const char* a_hi = (const char*)g.a_hi;
+    const char* a_lo = (const char*)g.a_lo;
+    const char* b_hi = (const char*)g.b_hi;
+    const char* b_lo = (const char*)g.b_lo;
+
+    for (int64_t tile = lg; tile < n_tiles; tile += G) {
+        const int ti = (int)(tile / n_tj), tj = (int)(tile % n_tj);
+        const int64_t row0 = (int64_t)ti * G_BM, col0 = (int64_t)tj * G_BN;
+
+        // global -> register staging: A tile = 128 rows x 64 B = 512 x 16 B,
+        // B tile = 256 rows x 64 B = 1024 x 16 B (per part)
+        uint4 ra[T::PARTS][2], rb[T::PARTS][4];
+        auto gload = [&](int c) {
+            const int64_t kb = (int64_t)c * T::KC * T::ES;
+#pragma unroll
+            for (int q = 0; q < T::PARTS; ++q) {
+                const char* sa = q ? a_lo : a_hi;
+                const char* sb = q ? b_lo : b_hi;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    int v = tid + G_THREADS * r;
+                    ra[q][r] = *reinterpret_cast<const uint4*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int v = tid + G_THREADS * r;
+                    rb[q][r] = *reinterpret_cast<const uint4*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+                }
+            }
+        };
+        auto sstore = [&](int stage) {
+            char* base = smem + stage * T::STAGE;
+#pragma unroll
+            for (int q = 0; q < T::PARTS; ++q) {
+                char* la = base + q * (G_BM + G_BN) * T::ROWB;
+                char* lb = la + G_BM * T::ROWB;
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    int v = tid + G_THREADS * r;
+                    *reinterpret_cast<uint4*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int v = tid + G_THREADS * r;
+                    *reinterpret_cast<uint4*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
+                }
+            }
+        };
+
+        f16_t acc[G_WM][G_WN];
+#pragma unroll
+        for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+            for (int j = 0; j < G_WN; ++j) acc[i][j] = f16_t{};
+
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int stage = c & 1;
+            if (c + 1 < n_chunks) gload(c + 1);
+            const char* base = smem + stage * T::STAGE;
+            const char* la_hi = base + (wr * 64 + (lane & 31)) * T::ROWB;
+            const char* lb_hi = base + G_BM * T::ROWB + (wc * 128 + (lane & 31)) * T::ROWB;
+            const int half = lane >> 5;
+            if constexpr (T::F32) {
+                // 8 K-steps of 2 per chunk; lane reads k = 8q + 4*half + e
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq) {
+                    float4 av[G_WM], bv[G_WN];
+#pragma unroll
+                    for (int i = 0; i < G_WM; ++i)
+                        av[i] = *reinterpret_cast<const float4*>(la_hi + i * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
+#pragma unroll
+                    for (int j = 0; j < G_WN; ++j)
+                        bv[j] = *reinterpret_cast<const float4*>(lb_hi + j * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                            for (int j = 0; j < G_WN; ++j)
+                                mfma_step<PREC>(acc[i][j], (const char*)&av[i], (const char*)&bv[j], e);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < T::KC / 16; ++s) {
+                    const int off = (s * 16 + half * 8) * 2;
+#pragma unroll
+                    for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                        for (int j = 0; j < G_WN; ++j) {
+                            const char* pa = la_hi + i * 32 * T::ROWB + off;
+                            const char* pb = lb_hi + j * 32 * T::ROWB + off;
+                            mfma_step<PREC>(acc[i][j], pa, pb, 0);
+                            if constexpr (T::SPLIT) {
+                                const int lo = (G_BM + G_BN) * T::ROWB;
+                                mfma_step<PREC>(acc[i][j], pa, pb + lo, 0);
+                                mfma_step<PREC>(acc[i][j], pa + lo, pb, 0);
+                            }
+                        }
+                }
+            }
+            if (c + 1 < n_chunks) {
+                sstore(stage ^ 1);
+            }
+            __syncthreads();
+        }
+
+        // ---- epilogue: fold |r| of this tile into the wave's running max
+        const bool edge = (row0 + G_BM > g.na) || (col0 + G_BN > g.nb);
+        const bool self = g.self_col != nullptr;
+        // 32x32 accumulator layout: register r of lane l holds
+        // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the block.
+        auto elem_row = [&](int i, int r) -> int64_t {
+            return row0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        };
+        auto elem_col = [&](int j) -> int64_t { return col0 + wc * 128 + j * 32 + (lane & 31); };
+        float m = -1.0f;
+        if (!edge && !self) {
+#pragma unroll
+            for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                for (int j = 0; j < G_WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; r += 2) m = fmaxf(m, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
+        } else {
+#pragma unroll
+            for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                for (int j = 0; j < G_WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        int64_t row = elem_row(i, r), col = elem_col(j);
+                        bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
+                        if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
+                    }
+        }
+        const float wm = wave_max(m);
+        if (wm >= 0.0f && wm >= best) {
+            // locate: smallest linear index among elements with |r| == wm
+            uint32_t cand = 0xffffffffu;
+            uint32_t neg = 0;
+#pragma unroll
+            for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                for (int j = 0; j < G_WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        float v = acc[i][j][r];
+                        int64_t row = elem_row(i, r), col = elem_col(j);
+                        bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
+                        uint32_t lin = (uint32_t)(row * g.nb + col);
+                        if (ok && fabsf(v) == wm && lin < cand) {
+                            cand = lin;
+                            neg = v < 0.0f ? 1u : 0u;
+                        }
+                    }
+            unsigned long long k = (cand == 0xffffffffu) ? 0ull : make_key(wm, cand, neg);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                unsigned long long o = __shfl_xor(k, off, 64);
+                k = o > k ? o : k;
+            }
+            best_key = k > best_key ? k : best_key;
+            best = wm;
+        }
+    }
+    if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
+}
+
+template <int PREC>
+static int launch_p(const GemmArgs& g, int num_cus, hipStream_t s) {
+    using T = GemmTraits<PREC>;
+    const int n_ti = (int)(g.na_pad / G_BM), n_tj = (int)(g.nb_pad / G_BN);
+    const int64_t n_tiles = (int64_t)n_ti * n_tj;
+    int64_t grid = (int64_t)num_cus * 2;
+    if (grid > n_tiles) grid = n_tiles;
+    const size_t lds = 2 * (size_t)T::STAGE;
+    static bool attr_set = false;
+    if (!attr_set) {
+        CORR_HIP(hipFuncSetAttribute((const void*)gemm_max_kernel<PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+        attr_set = true;
+    }
+    gemm_max_kernel<PREC><<<dim3((unsigned)grid), G_THREADS, lds, s>>>(g, n_ti, n_tj);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s) {
+    if (g.na == 0 || g.nb == 0) return CORR_OK;
+    switch (g.prec) {
+        case CORR_PREC_F32: return launch_p<CORR_PREC_F32>(g, num_cus, s);
+        case CORR_PREC_F16: return launch_p<CORR_PREC_F16>(g, num_cus, s);
+        case CORR_PREC_BF16: return launch_p<CORR_PREC_BF16>(g, num_cus, s);
+        case CORR_PREC_F16X3: return launch_p<CORR_PREC_F16X3>(g, num_cus, s);
+        case CORR_PREC_BF16X3: return launch_p<CORR_PREC_BF16X3>(g, num_cus, s);
+    }
+    return fail(CORR_EUNSUPPORTED, "unknown precision");
+}
+
+int gemm_row_pad() { return G_BM; }
+int gemm_col_pad() { return G_BN; }
+int gemm_k_pad(int prec) { return prec == CORR_PREC_F32 ? GemmTraits<CORR_PREC_F32>::KC : GemmTraits<CORR_PREC_F16>::KC; }
+
+}  // namespace corr

@@ -1,0 +1,148 @@
+// Pearson r for an explicit list of point pairs (Sec. 3.2).
+//
+// With the standardised rows Zhat[p][m] = (x_pm - mean_p) / sqrt(sum_m (x_pm -
+// mean_p)^2) (point-major, members contiguous), r = sum_m Zhat[a][m] Zhat[b][m].
+// A pair has no operand reuse, so this is a gather: G lanes per pair stream
+// the two rows with 16-byte loads and reduce with cross-lane shuffles.
+#include "common.h"
+
+namespace corr {
+
+template <int PREC>
+__device__ __forceinline__ float dot16(uint4 a, uint4 b) {
+    // 16 bytes = 8 x 16-bit (F16/BF16) or 4 x F32
+    float s = 0.0f;
+    if constexpr (PREC == CORR_PREC_F32) {
+        float4 x = *reinterpret_cast<float4*>(&a), y = *reinterpret_cast<float4*>(&b);
+        s = x.x * y.x;
+        s = fmaf(x.y, y.y, s);
+        s = fmaf(x.z, y.z, s);
+        s = fmaf(x.w, y.w, s);
+    } else {
+        const uint32_t* pa = reinterpret_cast<const uint32_t*>(&a);
+        const uint32_t* pb = reinterpret_cast<const uint32_t*>(&b);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            float a0, a1, b0, b1;
+            if constexpr (PREC == CORR_PREC_F16 || PREC == CORR_PREC_F16X3) {
+                __half2 ha = *reinterpret_cast<const __half2*>(&pa[w]);
+                __half2 hb = *reinterpret_cast<const __half2*>(&pb[w]);
+                float2 fa = __half22float2(ha), fb = __half22float2(hb);
+                a0 = fa.x; a1 = fa.y; b0 = fb.x; b1 = fb.y;
+            } else {
+                a0 = __uint_as_float(pa[w] << 16);
+                a1 = __uint_as_float(pa[w] & 0xffff0000u);
+                b0 = __uint_as_float(pb[w] << 16);
+                b1 = __uint_as_float(pb[w] & 0xffff0000u);
+            }
+            s = fmaf(a0, b0, s);
+            s = fmaf(a1, b1, s);
+        }
+    }
+    return s;
+}
+
+// G lanes per pair; each lane handles 16-byte chunks c = lane_in_group, +G, ...
+template <int PREC, int G>
+__global__ __launch_bounds__(256) void pearson_pairs_kernel(const uint4* __restrict__ ah, const uint4* __restrict__ al,
+                                                            const uint4* __restrict__ bh, const uint4* __restrict__ bl,
+                                                            int64_t ld_vec, const int32_t* __restrict__ pairs, int64_t n,
+                                                            float* __restrict__ r_out, Box ba, Box bb, int same_field,
+                                                            unsigned long long* key) {
+    constexpr bool SPLIT = (PREC == CORR_PREC_F16X3 || PREC == CORR_PREC_BF16X3);
+    constexpr int PER_WAVE = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int g = lane / G, gl = lane % G;
+    const int64_t nb = bb.count();
+    unsigned long long best = 0;
+    uint32_t cnt = 0;
+    const int64_t waves_total = (int64_t)gridDim.x * 4;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    for (int64_t base = wave_id * PER_WAVE; base < n; base += waves_total * PER_WAVE) {
+        const int64_t t = base + g;
+        const bool act = t < n;
+        int32_t ga = 0, gb = 0;
+        int64_t la = -1, lb = -1;
+        if (act) {
+            ga = pairs[2 * t];
+            gb = pairs[2 * t + 1];
+            la = ba.local(ga);
+            lb = bb.local(gb);
+        }
+        // rows of the standardised buffers are the boxes' local indices;
+        // a pair outside its box is not evaluated (r = 0, not in the max)
+        const bool ok = act && la >= 0 && lb >= 0;
+        float s = 0.0f;
+        if (ok) {
+            const uint4* pa = ah + la * ld_vec;
+            const uint4* pb = bh + lb * ld_vec;
+            for (int64_t c = gl; c < ld_vec; c += G) {
+                uint4 x = pa[c], y = pb[c];
+                s += dot16<PREC>(x, y);
+                if constexpr (SPLIT) {
+                    uint4 xl = (al + la * ld_vec)[c], yl = (bl + lb * ld_vec)[c];
+                    s += dot16<PREC>(x, yl) + dot16<PREC>(xl, y);
+                }
+            }
+        }
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        s = fminf(1.0f, fmaxf(-1.0f, s));
+        if (act && gl == 0) {
+            if (r_out) r_out[t] = s;
+            if (key && ok && !(same_field && ga == gb)) {
+                unsigned long long k = make_key(fabsf(s), (uint32_t)(la * nb + lb), s < 0.0f ? 1u : 0u);
+                best = k > best ? k : best;
+                ++cnt;
+            }
+        }
+    }
+    if (key) {
+        // wave reduction of the best key and the count, then one atomic per wave
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            unsigned long long o = __shfl_xor(best, off, 64);
+            best = o > best ? o : best;
+            cnt += __shfl_xor(cnt, off, 64);
+        }
+        if (lane == 0 && cnt) {
+            atomicMax(key, best);
+            atomicAdd(key + 1, (unsigned long long)cnt);
+        }
+    }
+}
+
+template <int PREC>
+static void launch_pp(int G, dim3 grid, const uint4* ah, const uint4* al, const uint4* bh, const uint4* bl,
+                      int64_t ld_vec, const int32_t* pairs, int64_t n, float* r, Box ba, Box bb, int sf,
+                      unsigned long long* key, hipStream_t s) {
+    if (G == 16)
+        pearson_pairs_kernel<PREC, 16><<<grid, 256, 0, s>>>(ah, al, bh, bl, ld_vec, pairs, n, r, ba, bb, sf, key);
+    else
+        pearson_pairs_kernel<PREC, 64><<<grid, 256, 0, s>>>(ah, al, bh, bl, ld_vec, pairs, n, r, ba, bb, sf, key);
+}
+
+int launch_pearson_pairs(int prec, const void* za_hi, const void* za_lo, const void* zb_hi, const void* zb_lo,
+                         int64_t ld, const int32_t* pairs, int64_t n, float* r_out, const Box& ba, const Box& bb,
+                         int same_field, unsigned long long* key, hipStream_t s) {
+    if (n == 0) return CORR_OK;
+    const int64_t ld_vec = ld * (int64_t)prec_elem_bytes(prec) / 16;
+    const int G = ld_vec <= 32 ? 16 : 64;
+    const int64_t per_block = 4 * (64 / G);
+    int64_t blocks = (n + per_block - 1) / per_block;
+    if (blocks > 65536) blocks = 65536;
+    dim3 grid((unsigned)blocks);
+    const uint4 *ah = (const uint4*)za_hi, *al = (const uint4*)za_lo, *bh = (const uint4*)zb_hi,
+                *bl = (const uint4*)zb_lo;
+    switch (prec) {
+        case CORR_PREC_F32: launch_pp<CORR_PREC_F32>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
+        case CORR_PREC_F16: launch_pp<CORR_PREC_F16>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
+        case CORR_PREC_BF16: launch_pp<CORR_PREC_BF16>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
+        case CORR_PREC_F16X3: launch_pp<CORR_PREC_F16X3>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
+        case CORR_PREC_BF16X3: launch_pp<CORR_PREC_BF16X3>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
+    }
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+}  // namespace corr

@@ -100,16 +100,34 @@ def _kernel_l2_norm(sigma: float, truncate: float) -> float:
 
 
 def smooth_noise(rng: np.random.Generator, M: int, nz: int, ny: int, nx: int,
-                 sigma: float = SMOOTH_SIGMA, chunk: int = 64) -> np.ndarray:
-    """Unit-variance periodic smoothed white noise, shape (M, nz, ny, nx), float32."""
+                 sigma: float = SMOOTH_SIGMA, chunk: int = 64, threads: int = 0) -> np.ndarray:
+    """Unit-variance periodic smoothed white noise, shape (M, nz, ny, nx), float32.
+
+    The noise is drawn chunk by chunk in member order (so the result does not
+    depend on ``threads``); the smoothing of the chunks runs on a thread pool.
+    """
+    import concurrent.futures
+    import os
+
     out = np.empty((M, nz, ny, nx), dtype=np.float32)
-    norm = _kernel_l2_norm(sigma, SMOOTH_TRUNCATE)
-    for m0 in range(0, M, chunk):
-        m1 = min(M, m0 + chunk)
-        w = rng.standard_normal((m1 - m0, nz, ny, nx), dtype=np.float32)
+    norm = np.float32(_kernel_l2_norm(sigma, SMOOTH_TRUNCATE))
+
+    def smooth(m0, w):
         ndi.gaussian_filter(w, sigma=(0.0, sigma, sigma, sigma), mode="wrap",
-                            truncate=SMOOTH_TRUNCATE, output=out[m0:m1])
-        out[m0:m1] /= np.float32(norm)
+                            truncate=SMOOTH_TRUNCATE, output=out[m0:m0 + w.shape[0]])
+        out[m0:m0 + w.shape[0]] /= norm
+
+    n_threads = threads or min(16, os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=n_threads) as ex:
+        futs = []
+        for m0 in range(0, M, chunk):
+            m1 = min(M, m0 + chunk)
+            w = rng.standard_normal((m1 - m0, nz, ny, nx), dtype=np.float32)
+            futs.append(ex.submit(smooth, m0, w))
+            if len(futs) >= 2 * n_threads:
+                futs.pop(0).result()
+        for f in futs:
+            f.result()
     return out
 
 

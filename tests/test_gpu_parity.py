@@ -1,0 +1,321 @@
+"""GPU parity: libcorr (through its C ABI) against the CPU oracle on the same
+seeded inputs.
+
+Bars: KSG neighbour counts bit-exact; KSG MI within 1e-5; Pearson within
+1e-5 (FP32 operands and the split hi/lo modes), within the single-pass
+16-bit error bound 2u + u^2 (FP16: 9.8e-4, stated 2e-3) and within the BF16
+worst-case bound 2u + u^2 = 7.8e-3 (its observed maximum is printed).
+Region maxima: value within the measure's tolerance; argmax exact whenever
+the oracle's top-2 gap exceeds that tolerance (otherwise both are correct).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 7.9e-3, "f16x3": 1e-5, "bf16x3": 3e-5}
+MODES = ["f32", "f16", "bf16", "f16x3", "bf16x3"]
+MI_TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def pc():
+    import __graft_entry__ as g
+    g._ensure_built()
+    import paper_2309_03308_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(pc):
+    c = pc.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.make_cfg1()
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return synth.make_cfg2()
+
+
+def _field(pc, torch, e):
+    return pc.Field(dev(torch, e.data), e.nx, e.ny, e.nz)
+
+
+def _all_pairs(e):
+    ia = e.regions[0].global_indices(e.nx, e.ny)
+    ib = e.regions[1].global_indices(e.nx, e.ny)
+    return ia, ib, np.stack(np.meshgrid(ia, ib, indexing="ij"), -1).reshape(-1, 2).astype(np.int32)
+
+
+# ------------------------------------------------------------ standardisation
+def test_standardize_bitwise(ctx, pc, torch, cfg1, cfg2):
+    for e in (cfg1, cfg2):
+        _say(f"standardize {e.name}")
+        f = _field(pc, torch, e)
+        mu, inv, sig = ctx.corr_standardize(f)
+        torch.cuda.synchronize()
+        _, s2, mu32, inv32 = oracle.stats(e.data)
+        assert np.array_equal(mu.cpu().numpy(), mu32)
+        assert np.array_equal(inv.cpu().numpy(), inv32)
+        ref_sig = np.sqrt(s2 / e.M)
+        assert np.allclose(sig.cpu().numpy(), ref_sig, rtol=1e-6)
+
+
+# ------------------------------------------------------------ Pearson pairs
+@pytest.mark.parametrize("prec", MODES)
+def test_pearson_pairs_cfg1(ctx, pc, torch, cfg1, prec):
+    _say(f"pearson pairs cfg1 {prec}")
+    ia, ib, pairs = _all_pairs(cfg1)
+    f = _field(pc, torch, cfg1)
+    r = ctx.corr_pearson_pairs(f, dev(torch, pairs), prec).cpu().numpy()
+    ref = oracle.pearson_pairs(cfg1.data, pairs)
+    err = np.max(np.abs(r - ref))
+    _say(f"  max |err| {prec} = {err:.3e}")
+    assert err <= TOL[prec]
+    assert np.all(np.abs(r) <= 1.0)
+
+
+# ------------------------------------------------------------ KSG
+def test_ksg_counts_bit_exact_cfg1(ctx, pc, torch, cfg1):
+    _say("ksg counts cfg1 (65536 pairs)")
+    ia, ib, pairs = _all_pairs(cfg1)
+    f = _field(pc, torch, cfg1)
+    mi, cnt = ctx.corr_ksg_mi_pairs(f, dev(torch, pairs), k=10, counts=True)
+    mi_ref, cnt_ref = oracle.ksg_pairs(cfg1.data, pairs, 10)
+    cnt = cnt.cpu().numpy()
+    assert np.array_equal(cnt, cnt_ref), f"{int((cnt != cnt_ref).sum())} counts differ"
+    assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
+
+
+def test_ksg_raw_identical_fp32_inputs(ctx, pc, torch, cfg1):
+    # the oracle's own z-scored FP32 samples are the GPU's input (RAW flag)
+    _say("ksg raw identical inputs")
+    ia, ib, pairs = _all_pairs(cfg1)
+    z = oracle.ksg_inputs(cfg1.data, np.arange(cfg1.P, dtype=np.int32))  # (P, M)
+    zf = pc.Field(dev(torch, np.ascontiguousarray(z.T)), cfg1.nx, cfg1.ny, cfg1.nz)
+    mi, cnt = ctx.corr_ksg_mi_pairs(zf, dev(torch, pairs), k=10, raw=True, counts=True)
+    mi_ref, cnt_ref = oracle.ksg_rows(z, z, pairs, 10)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+    assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
+
+
+@pytest.mark.parametrize("k", [1, 3, 10, 31])
+def test_ksg_k_values(ctx, pc, torch, cfg1, k):
+    rng = np.random.default_rng(k)
+    pairs = rng.integers(0, cfg1.P, (4000, 2)).astype(np.int32)
+    f = _field(pc, torch, cfg1)
+    mi, cnt = ctx.corr_ksg_mi_pairs(f, dev(torch, pairs), k=k, counts=True)
+    mi_ref, cnt_ref = oracle.ksg_pairs(cfg1.data, pairs, k)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+    assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
+
+
+def test_ksg_ties_and_small_M(ctx, pc, torch):
+    # coarse values force exact ties in distances (multiset eps) and eps = 0
+    rng = np.random.default_rng(7)
+    for M in (5, 11, 64, 65, 129):
+        data = np.round(rng.standard_normal((M, 40)) * 2).astype(np.float32) / 2
+        data[:, 3] = data[:, 4]  # identical rows
+        pairs = np.stack([rng.integers(0, 40, 600), rng.integers(0, 40, 600)], 1).astype(np.int32)
+        pairs[0] = (3, 4)
+        f = pc.Field(dev(torch, data), 40, 1, 1)
+        k = min(4, M - 1)
+        for raw in (False, True):
+            mi, cnt = ctx.corr_ksg_mi_pairs(f, dev(torch, pairs), k=k, raw=raw, counts=True)
+            mi_ref, cnt_ref = oracle.ksg_pairs(data, pairs, k, raw=raw)
+            assert np.array_equal(cnt.cpu().numpy(), cnt_ref), (M, raw)
+            assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
+
+
+# ------------------------------------------------------------ region maxima
+@pytest.mark.parametrize("prec", MODES)
+def test_region_max_pearson_cfg1(ctx, pc, torch, cfg1, prec):
+    ia, ib, _ = _all_pairs(cfg1)
+    f = _field(pc, torch, cfg1)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg1.regions]
+    got = ctx.corr_region_max(f, ra, rb, "pearson", prec)
+    ref = oracle.pearson_region_max_matmul(cfg1.data, ia, ib)
+    _say(f"  region max {prec}: gpu {got['value']:.7f} oracle {ref['value']:.7f}")
+    assert abs(got["value"] - ref["value"]) <= TOL[prec]
+    assert got["n_evaluated"] == ia.size * ib.size
+    if ref["value"] - ref["second"] > 2 * TOL[prec]:
+        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+        assert np.sign(got["signed_value"]) == np.sign(ref["signed_value"])
+
+
+def test_region_max_ksg_cfg1_exhaustive(ctx, pc, torch, cfg1):
+    ia, ib, pairs = _all_pairs(cfg1)
+    f = _field(pc, torch, cfg1)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg1.regions]
+    got = ctx.corr_region_max(f, ra, rb, "ksg", k=10)
+    mi, _ = oracle.ksg_pairs(cfg1.data, pairs, 10, want_counts=False)
+    la = np.repeat(np.arange(ia.size), ib.size)
+    lb = np.tile(np.arange(ib.size), ia.size)
+    ref = oracle.region_max_from_values(mi, la, lb, pairs[:, 0], pairs[:, 1], use_abs=False)
+    assert abs(got["value"] - ref["value"]) <= MI_TOL
+    assert got["n_evaluated"] == ia.size * ib.size
+    top = np.sort(mi)[-2:]
+    if top[1] - top[0] > 2 * MI_TOL:
+        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+
+
+def test_region_max_planted_copy(ctx, pc, torch):
+    e = synth.make_cfg1(copy_variant=True)
+    p, q = e.copy_pair
+    f = _field(pc, torch, e)
+    ra, rb = [pc.region(*r.as_tuple()) for r in e.regions]
+    ref = oracle.pearson_region_max_matmul(e.data, e.regions[0].global_indices(e.nx, e.ny),
+                                           e.regions[1].global_indices(e.nx, e.ny))
+    assert (ref["pa"], ref["pb"]) == (p, q)
+    for prec in MODES:
+        got = ctx.corr_region_max(f, ra, rb, "pearson", prec)
+        assert abs(got["value"] - 1.0) <= TOL[prec], (prec, got)
+        # the copy is the unique argmax only where the top-2 gap exceeds the mode's error
+        if ref["value"] - ref["second"] > 2 * TOL[prec]:
+            assert (got["pa"], got["pb"]) == (p, q), (prec, got)
+    got = ctx.corr_region_max(f, ra, rb, "ksg", k=10)
+    assert abs(got["value"] - (oracle.digamma_int(100) - oracle.digamma_int(10))) <= MI_TOL
+    assert (got["pa"], got["pb"]) == (p, q)
+
+
+def test_region_max_self_overlap(ctx, pc, torch, cfg1):
+    # A = B (self-correlation refinement of one brick): pA == pB is skipped
+    ia = cfg1.regions[0].global_indices(cfg1.nx, cfg1.ny)
+    f = _field(pc, torch, cfg1)
+    ra = pc.region(*cfg1.regions[0].as_tuple())
+    rpart = pc.region(4, 0, 0, 8, 8, 4)  # partial overlap with A
+    ref = oracle.pearson_region_max_matmul(cfg1.data, ia, ia)
+    for prec in ("f32", "f16x3"):
+        got = ctx.corr_region_max(f, ra, ra, "pearson", prec)
+        assert got["value"] < 0.999999 and abs(got["value"] - ref["value"]) <= TOL[prec]
+        assert got["n_evaluated"] == ia.size * (ia.size - 1)
+    ib = synth.Region(4, 0, 0, 8, 8, 4).global_indices(cfg1.nx, cfg1.ny)
+    ref2 = oracle.pearson_region_max_matmul(cfg1.data, ia, ib)
+    got2 = ctx.corr_region_max(f, ra, rpart, "pearson", "f32")
+    assert abs(got2["value"] - ref2["value"]) <= 1e-5
+    assert got2["n_evaluated"] == ref2["n_evaluated"]
+
+
+def test_region_max_sampled_lists(ctx, pc, torch, cfg1):
+    ia, ib, pairs = _all_pairs(cfg1)
+    rng = np.random.default_rng(3)
+    s = pairs[rng.choice(pairs.shape[0], 3000, replace=False)]
+    f = _field(pc, torch, cfg1)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg1.regions]
+    la = np.searchsorted(ia, s[:, 0])
+    lb = np.searchsorted(ib, s[:, 1])
+    r = oracle.pearson_pairs(cfg1.data, s)
+    ref = oracle.region_max_from_values(r, la, lb, s[:, 0], s[:, 1], use_abs=True)
+    got = ctx.corr_region_max(f, ra, rb, "pearson", "f32", samples=dev(torch, s))
+    assert abs(got["value"] - ref["value"]) <= 1e-5 and got["n_evaluated"] == 3000
+    mi, _ = oracle.ksg_pairs(cfg1.data, s, 10, want_counts=False)
+    ref = oracle.region_max_from_values(mi, la, lb, s[:, 0], s[:, 1], use_abs=False)
+    got = ctx.corr_region_max(f, ra, rb, "ksg", k=10, samples=dev(torch, s))
+    assert abs(got["value"] - ref["value"]) <= MI_TOL and (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+
+
+# ------------------------------------------------------------ focus view (80x32x20, M=100)
+@pytest.mark.parametrize("prec", MODES)
+def test_cfg2_pearson_region_max(ctx, pc, torch, cfg2, prec):
+    _say(f"cfg2 pearson region max {prec}")
+    ia = cfg2.regions[0].global_indices(cfg2.nx, cfg2.ny)
+    ib = cfg2.regions[1].global_indices(cfg2.nx, cfg2.ny)
+    f = _field(pc, torch, cfg2)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg2.regions]
+    got = ctx.corr_region_max(f, ra, rb, "pearson", prec)
+    ref = _cfg2_ref(cfg2, ia, ib)
+    _say(f"  gpu {got['value']:.7f} oracle {ref['value']:.7f} second {ref['second']:.7f}")
+    assert abs(got["value"] - ref["value"]) <= TOL[prec]
+    assert got["n_evaluated"] == ia.size * ib.size == 419430400
+    if ref["value"] - ref["second"] > 2 * TOL[prec]:
+        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+
+
+_CFG2_REF = {}
+
+
+def _cfg2_ref(e, ia, ib):
+    if "r" not in _CFG2_REF:
+        _CFG2_REF["r"] = oracle.pearson_region_max_matmul(e.data, ia, ib, block=2048)
+    return _CFG2_REF["r"]
+
+
+def test_cfg2_ksg_full_pair_list(ctx, pc, torch, cfg2):
+    # the full 1e6-pair launch; the oracle recomputes a seeded sample of its outputs
+    _say("cfg2 ksg 1e6 pairs")
+    pairs = synth.region_pairs_uniform(102, 1_000_000, cfg2.regions[0], cfg2.regions[1], cfg2.nx, cfg2.ny)
+    f = _field(pc, torch, cfg2)
+    mi = ctx.corr_ksg_mi_pairs(f, dev(torch, pairs), k=10).cpu().numpy()
+    sel = np.random.default_rng(5).choice(pairs.shape[0], 20000, replace=False)
+    mi_ref, _ = oracle.ksg_pairs(cfg2.data, pairs[sel], 10, want_counts=False)
+    assert np.max(np.abs(mi[sel] - mi_ref)) <= MI_TOL
+    # neighbour counts of a 5000-pair sub-list, bit-exact
+    sub = pairs[sel[:5000]]
+    _, cnt = ctx.corr_ksg_mi_pairs(f, dev(torch, sub), k=10, counts=True)
+    _, cnt_ref = oracle.ksg_pairs(cfg2.data, sub, 10)
+    assert np.array_equal(cnt.cpu().numpy(), cnt_ref)
+
+
+# ------------------------------------------------------------ API behaviour
+def test_error_paths(ctx, pc, torch, cfg1):
+    f = _field(pc, torch, cfg1)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg1.regions]
+    pairs = dev(torch, np.zeros((4, 2), np.int32))
+    with pytest.raises(pc.CorrError) as ei:
+        ctx.corr_ksg_mi_pairs(f, pairs, k=100)
+    assert ei.value.status == 1
+    with pytest.raises(pc.CorrError) as ei:
+        ctx.corr_ksg_mi_pairs(f, pairs, k=0)
+    assert ei.value.status == 1
+    with pytest.raises(pc.CorrError) as ei:
+        ctx.corr_region_max(f, pc.region(10, 0, 0, 8, 8, 4), rb)
+    assert ei.value.status == 1
+    with pytest.raises(pc.CorrError) as ei:
+        ctx.corr_region_max(f, ra, pc.region(0, 0, 0, 0, 8, 4))
+    assert ei.value.status == 1
+    g = pc.Field(dev(torch, cfg1.data[:50]), cfg1.nx, cfg1.ny, cfg1.nz)
+    with pytest.raises(pc.CorrError) as ei:
+        ctx.corr_pearson_pairs(f, pairs, "f32", B=g)
+    assert ei.value.status == 1
+    # empty inputs are fine
+    empty = dev(torch, np.zeros((0, 2), np.int32))
+    assert ctx.corr_pearson_pairs(f, empty).numel() == 0
+    assert ctx.corr_ksg_mi_pairs(f, empty).numel() == 0
+
+
+def test_determinism(ctx, pc, torch, cfg2):
+    f = _field(pc, torch, cfg2)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg2.regions]
+    a = ctx.corr_region_max(f, ra, rb, "pearson", "f16")
+    b = ctx.corr_region_max(f, ra, rb, "pearson", "f16")
+    assert a == b
+    pairs = dev(torch, synth.region_pairs_uniform(9, 50000, cfg2.regions[0], cfg2.regions[1], cfg2.nx, cfg2.ny))
+    m1 = ctx.corr_ksg_mi_pairs(f, pairs).cpu().numpy()
+    m2 = ctx.corr_ksg_mi_pairs(f, pairs).cpu().numpy()
+    assert np.array_equal(m1, m2)

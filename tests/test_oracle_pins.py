@@ -209,3 +209,24 @@ def test_region_max_tie_break_smallest_local_index():
     lb = np.array([0, 0, 5, 4, 0], np.int32)
     assert oracle.argmax_pairs(vals, la, lb, use_abs=True) == 3  # (1,4) beats (1,5) and (2,0)
     assert oracle.argmax_pairs(vals, la, lb, use_abs=False) == 2
+
+
+def test_matmul_region_max_agrees_with_brute_force():
+    # the FP64 matrix-product route must agree with the plain loop on every case
+    for e in (synth.make_cfg1(), synth.make_cfg1(copy_variant=True)):
+        ia = e.regions[0].global_indices(e.nx, e.ny)
+        ib = e.regions[1].global_indices(e.nx, e.ny)
+        a = oracle.pearson_region_max(e.data, ia, ib)
+        b = oracle.pearson_region_max_matmul(e.data, ia, ib, block=100)
+        assert b["value"] == pytest.approx(a["value"], abs=1e-13)
+        assert (b["la"], b["lb"]) == (a["la"], a["lb"])
+        assert b["signed_value"] == pytest.approx(a["signed_value"], abs=1e-13)
+        assert b["second"] <= b["value"]
+    # overlapping regions of one field: the self pair is skipped
+    e = synth.make_cfg1()
+    ia = e.regions[0].global_indices(e.nx, e.ny)
+    a = oracle.pearson_region_max(e.data, ia, ia)
+    b = oracle.pearson_region_max_matmul(e.data, ia, ia, block=64)
+    assert a["value"] < 1.0 and b["value"] == pytest.approx(a["value"], abs=1e-13)
+    assert (b["la"], b["lb"]) == (a["la"], a["lb"])
+    assert a["n_evaluated"] == b["n_evaluated"] == ia.size * (ia.size - 1)
