@@ -1,0 +1,192 @@
+"""Benchmark of the correlation hot path on one MI355X.
+
+Workload (the focus-view refinement configuration): an 80x32x20 ensemble with
+M = 100 members (FP32, seeded smoothed-Gaussian field with 3 planted
+correlated blobs), regions A = x in [0,32) and B = x in [48,80) of 32x32x20 =
+20,480 points each. One step is one pass of the focus view:
+
+  * Pearson: every one of the 4.19e8 (pA, pB) pairs, standardised and
+    contracted on MFMA (FP16 operands, FP32 accumulation) with the region
+    maximum fused into the epilogue (corr_region_max, exhaustive);
+  * KSG mutual information (k = 10) on a uniform 1e6-pair sample of A x B,
+    with its region maximum fused (corr_region_max over the sample list).
+
+value = (Pearson pairs + KSG pairs) per second of step time, inputs resident
+in HBM. The JSON line also carries the per-measure rates, a roofline entry for
+the dominant kernel (timed live with HIP events on the stream it runs on) and
+the CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_PEARSON = 20480 * 20480
+N_KSG = 1_000_000
+M = 100
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+MFMA_F16_PEAK = 2.5e15
+HBM_PEAK = 8.0e12
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
+    """The oracle as it stands, timed on host cores over a bounded sample."""
+    import oracle
+    rng = np.random.default_rng(77)
+    ia = e.regions[0].global_indices(e.nx, e.ny)
+    ib = e.regions[1].global_indices(e.nx, e.ny)
+    n_p = 2_000_000
+    ps = np.stack([rng.choice(ia, n_p), rng.choice(ib, n_p)], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    r_ref = oracle.pearson_pairs(e.data, ps)
+    t_p = (time.perf_counter() - t0) / n_p
+    n_k = 20_000
+    ks = pairs_np[rng.choice(pairs_np.shape[0], n_k, replace=False)]
+    t0 = time.perf_counter()
+    mi_ref, cnt_ref = oracle.ksg_pairs(e.data, ks, 10)
+    t_k = (time.perf_counter() - t0) / n_k
+    t_step = N_PEARSON * t_p + N_KSG * t_k
+    # errors of the GPU path on the same sample
+    r_gpu = ctx.corr_pearson_pairs(f, torch.from_numpy(ps).cuda(), "f16").cpu().numpy()
+    mi_gpu, cnt_gpu = ctx.corr_ksg_mi_pairs(f, torch.from_numpy(ks).cuda(), k=10, counts=True)
+    ref_max = oracle.pearson_region_max_matmul(e.data, ia, ib, block=2048)
+    err = {
+        "pearson_f16_pairs_max_abs": float(np.max(np.abs(r_gpu - r_ref))),
+        "pearson_region_max_abs": float(abs(ctx_results["pearson"]["value"] - ref_max["value"])),
+        "ksg_mi_max_abs": float(np.max(np.abs(mi_gpu.cpu().numpy() - mi_ref))),
+        "ksg_count_mismatches": int((cnt_gpu.cpu().numpy() != cnt_ref).sum()),
+    }
+    return {
+        "value": (N_PEARSON + N_KSG) / t_step,
+        "unit": "point pairs/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 Pearson on {n_p} uniform A x B pairs ({t_p * 1e9:.1f} ns/pair) and brute-force KSG on "
+                   f"{n_k} of the 1e6 sampled pairs ({t_k * 1e6:.1f} us/pair), extrapolated to one step "
+                   f"(4.19e8 Pearson + 1e6 KSG pairs)"),
+        "cpu_model": cpu_model(),
+    }, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path has no multi-GPU mode in this build "
+              "(region pairs would shard across GPUs; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import __graft_entry__ as g
+    g._ensure_built()
+    import paper_2309_03308_amd as pc
+
+    e = synth.make_cfg2()
+    pairs_np = synth.region_pairs_uniform(102, N_KSG, e.regions[0], e.regions[1], e.nx, e.ny)
+    ctx = pc.Context(0)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    pairs = torch.from_numpy(pairs_np).cuda()
+    ra, rb = [pc.region(*r.as_tuple()) for r in e.regions]
+    ctx.set_timing(True)
+    res = {}
+
+    def step():
+        res["pearson"] = ctx.corr_region_max(f, ra, rb, "pearson", args.prec)
+        res["ksg"] = ctx.corr_region_max(f, ra, rb, "ksg", k=10, samples=pairs)
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    k_gemm, k_ksg = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        k_gemm.append(ctx.kernel_time_ms("gemm"))
+        k_ksg.append(ctx.kernel_time_ms("ksg"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = (N_PEARSON + N_KSG) / (ms / 1e3)
+    gemm_ms = float(np.mean(k_gemm))
+    ksg_ms = float(np.mean(k_ksg))
+
+    # roofline of the dominant kernel (KSG): algorithmic work = M(M-1) Chebyshev
+    # distance evaluations per pair, 3 VALU lane-ops each (2 sub + max|.|)
+    ksg_ops = N_KSG * M * (M - 1) * 3.0
+    achieved = ksg_ops / (ksg_ms / 1e3) / 1e12
+    peak = VALU_LANE_OPS_PER_S / 1e12
+    line = {
+        "metric": "point pairs/s for Pearson & KSG-MI at M=100/1000; max-err vs FP64 oracle",
+        "value": value,
+        "unit": "point pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "focus-view refinement: 80x32x20 ensemble, M=100 FP32, regions 32x32x20 x 2, "
+                               "Pearson all 4.19e8 pairs (fused region max) + KSG k=10 on 1e6 sampled pairs",
+                   "members": M, "pearson_pairs": N_PEARSON, "ksg_pairs": N_KSG, "k": 10,
+                   "pearson_precision": args.prec},
+        "breakdown": {
+            "pearson_region_max_kernel_ms": gemm_ms,
+            "pearson_pairs_per_s_kernel": N_PEARSON / (gemm_ms / 1e3),
+            "pearson_mfma_tflops_algorithmic": 2.0 * M * N_PEARSON / (gemm_ms / 1e3) / 1e12,
+            "pearson_mfma_frac_of_f16_peak": 2.0 * M * N_PEARSON / (gemm_ms / 1e3) / MFMA_F16_PEAK,
+            "ksg_kernel_ms": ksg_ms,
+            "ksg_pairs_per_s_kernel": N_KSG / (ksg_ms / 1e3),
+            "pearson_max": res["pearson"]["value"],
+            "ksg_max": res["ksg"]["value"],
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
+                     "traffic": None, "kernel": "ksg_kernel<11,2>",
+                     "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair"},
+    }
+    if not args.no_cpu_baseline:
+        cb, err = cpu_baseline(e, pairs_np, res, f, ctx, torch, pc)
+        line["cpu_baseline"] = cb
+        line["max_err_vs_fp64_oracle"] = err
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

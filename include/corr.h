@@ -169,6 +169,45 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
                     const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
                     int64_t n_samples, corr_max* out, corr_stream_t stream);
 
+/*
+ * Autotuner for the exhaustive Pearson contraction (tile shapes of the
+ * small-ensemble kernel, M <= 128): runs every tile configuration valid for
+ * `prec` on the given region pair `reps` times, timing the contraction kernel
+ * with HIP events, and records the fastest (median) in the context's table;
+ * later corr_region_max calls of the same shape use it. best_cfg / best_ms
+ * (HOST, nullable) receive the choice (-1 when M > 128: nothing to tune).
+ * Synchronises `stream`.
+ */
+int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                  const corr_region* rb, int prec, int reps, int* best_cfg, float* best_ms, corr_stream_t stream);
+
+/*
+ * Autotuner for the KSG pair mapping (Sec. 3.2 estimator; how many pairs one
+ * wave stages and spreads its (pair, sample) items over): times each
+ * candidate on the given pair list (as corr_ksg_mi_pairs would run it) and
+ * records the fastest for (M, k). best_pw / best_ms HOST, nullable.
+ * Synchronises `stream`.
+ */
+int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
+                      int32_t k, int reps, int* best_pw, float* best_ms, corr_stream_t stream);
+
+/* Write / read the context's tuning table as JSON lines (one record per
+ * line: arch, kind, K, prec, na, nb, cfg, ms). Loading merges into the
+ * table; malformed or out-of-range records are skipped. */
+int corr_tune_save(corr_ctx* ctx, const char* path);
+int corr_tune_load(corr_ctx* ctx, const char* path);
+
+/*
+ * Kernel timing hook (instrumentation, no effect on results). With timing
+ * on, the main kernel of each call is bracketed by HIP events recorded on the
+ * call's stream. corr_kernel_time_ms waits for the last such kernel of class
+ * `which` and returns its duration in milliseconds (-1 if none yet).
+ * which: 0 = Pearson contraction (exhaustive region max), 1 = KSG,
+ *        2 = Pearson pair list, 3 = standardisation (statistics + layout).
+ */
+int corr_set_timing(corr_ctx* ctx, int on);
+int corr_kernel_time_ms(corr_ctx* ctx, int which, float* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,7 @@ def lib():
         L.orc_argmax_pairs.argtypes = [P, P, P, I64, I]
         L.orc_argmax_pairs.restype = I64
         L.orc_pearson_region_max.argtypes = [P, I64, P, I64, P, I64, P, I64, I, I, P, P, P, P, P]
+        L.orc_num_threads.restype = I
         _lib = L
     return _lib
 
@@ -70,6 +71,10 @@ def _f32(data):
     if d.dtype != np.float32:
         d = d.astype(np.float32)  # exact for float16
     return d
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def digamma_int(n: int) -> float:

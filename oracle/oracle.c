@@ -268,3 +268,7 @@ void orc_pearson_region_max(const float* xa, int64_t sa, const int32_t* pa, int6
     free(ma); free(qa); free(mb); free(qb);
     free(rowv); free(rows); free(rowj); free(rown);
 }
+
+/* Threads an OpenMP parallel region of the oracle uses. */
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }

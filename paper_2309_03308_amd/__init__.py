@@ -83,6 +83,41 @@ class Context:
         except Exception:
             pass
 
+    # ------------------------------------------------------------------ timing
+    KERNEL_CLASSES = {"gemm": 0, "ksg": 1, "pairs": 2, "standardize": 3}
+
+    def set_timing(self, on: bool = True):
+        _lib.check(self.L.corr_set_timing(self.h, 1 if on else 0))
+
+    def kernel_time_ms(self, which: str) -> float:
+        ms = ctypes.c_float()
+        _lib.check(self.L.corr_kernel_time_ms(self.h, self.KERNEL_CLASSES[which], ctypes.byref(ms)))
+        return float(ms.value)
+
+    # ------------------------------------------------------------------ tuning
+    def corr_autotune(self, A: Field, ra: corr_region, rb: corr_region, prec="f16", reps=5, B: Field = None,
+                      stream=None):
+        B = A if B is None else B
+        cfg, ms = ctypes.c_int(), ctypes.c_float()
+        _lib.check(self.L.corr_autotune(self.h, ctypes.byref(A.c), ctypes.byref(ra), ctypes.byref(B.c),
+                                        ctypes.byref(rb), PREC[prec], int(reps), ctypes.byref(cfg), ctypes.byref(ms),
+                                        _stream_ptr(stream)))
+        return int(cfg.value), float(ms.value)
+
+    def corr_ksg_autotune(self, A: Field, pairs, k=10, reps=3, B: Field = None, stream=None):
+        B = A if B is None else B
+        pp, n = _pairs_arg(pairs)
+        pw, ms = ctypes.c_int(), ctypes.c_float()
+        _lib.check(self.L.corr_ksg_autotune(self.h, ctypes.byref(A.c), ctypes.byref(B.c), pp, n, int(k), int(reps),
+                                            ctypes.byref(pw), ctypes.byref(ms), _stream_ptr(stream)))
+        return int(pw.value), float(ms.value)
+
+    def corr_tune_save(self, path: str):
+        _lib.check(self.L.corr_tune_save(self.h, path.encode()))
+
+    def corr_tune_load(self, path: str):
+        _lib.check(self.L.corr_tune_load(self.h, path.encode()))
+
     # ------------------------------------------------------------------ calls
     def corr_standardize(self, A: Field, stream=None):
         torch = _torch()

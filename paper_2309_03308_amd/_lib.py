@@ -58,6 +58,14 @@ SIGNATURES = {
                                _P, _P, _P]),
     "corr_region_max": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), ctypes.POINTER(corr_field),
                              ctypes.POINTER(corr_region), _I, _I, _I32, _P, _I64, ctypes.POINTER(corr_max), _P]),
+    "corr_autotune": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), ctypes.POINTER(corr_field),
+                           ctypes.POINTER(corr_region), _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float), _P]),
+    "corr_ksg_autotune": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I64, _I32, _I,
+                               ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float), _P]),
+    "corr_tune_save": (_I, [_P, ctypes.c_char_p]),
+    "corr_tune_load": (_I, [_P, ctypes.c_char_p]),
+    "corr_set_timing": (_I, [_P, _I]),
+    "corr_kernel_time_ms": (_I, [_P, _I, ctypes.POINTER(ctypes.c_float)]),
 }
 
 

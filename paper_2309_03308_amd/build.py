@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libcorr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "standardize.hip", "pairs.hip", "ksg.hip", "gemm.hip"]
+SOURCES = ["api.hip", "standardize.hip", "pairs.hip", "ksg.hip", "gemm.hip", "gemm_smallk.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

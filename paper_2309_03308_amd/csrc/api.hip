@@ -1,4 +1,5 @@
 // Host side of the C ABI: validation, contexts, workspaces, dispatch.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -56,9 +57,16 @@ __global__ void self_col_kernel(Box a, Box b, int32_t* out) {
     if (i < a.count()) out[i] = (int32_t)b.local(a.global(i));
 }
 
-int gemm_row_pad();
-int gemm_col_pad();
-int gemm_k_pad(int prec);
+void timing_begin(corr_ctx* ctx, int which, hipStream_t s) {
+    if (ctx->timing) (void)hipEventRecord(ctx->ev_start[which], s);
+}
+
+void timing_end(corr_ctx* ctx, int which, hipStream_t s) {
+    if (ctx->timing) {
+        (void)hipEventRecord(ctx->ev_stop[which], s);
+        ctx->ev_valid[which] = true;
+    }
+}
 
 // ---- validation -------------------------------------------------------------
 static int64_t field_points(const corr_field& f) { return (int64_t)f.nx * f.ny * f.nz; }
@@ -143,6 +151,14 @@ static int standardize_box(corr_ctx* ctx, const corr_field& f, const Box& box, b
     return CORR_OK;
 }
 
+// Each standardised row sorted ascending (the marginals KSG counts on).
+static int sorted_rows(corr_ctx* ctx, const float* z, int64_t ld, int64_t nrows, int M, int slot, hipStream_t s,
+                       void** out) {
+    int rc = ws_get(ctx, slot, sizeof(float) * (size_t)nrows * ksg_p2(M), s, out);
+    if (rc) return rc;
+    return launch_sort_rows(z, ld, nrows, M, (float*)*out, ctx->num_cus, s);
+}
+
 static int read_keys(corr_ctx* ctx, hipStream_t s, unsigned long long* k0, unsigned long long* k1) {
     CORR_HIP(hipMemcpyAsync(ctx->keys_host, ctx->keys, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipStreamSynchronize(s));
@@ -166,6 +182,89 @@ static void decode_key(unsigned long long key, const Box& ba, const Box& bb, boo
     out->signed_value = (is_abs && (key & 1ull)) ? -v : v;
     out->pa = ba.global(la);
     out->pb = bb.global(lb);
+}
+
+// Default small-K tile configuration before any tuning: measured fastest on
+// gfx950 for the 20480 x 20480 focus-view shape.
+static int default_smallk_cfg(int prec) { return prec_split(prec) ? 1 : 0; }
+
+static int tuned_smallk_cfg(corr_ctx* ctx, int K, int prec, int64_t na, int64_t nb) {
+    for (const corr_tune_rec& r : ctx->tune)
+        if (r.kind == 0 && r.K == K && r.prec == prec && r.na == na && r.nb == nb) return r.cfg;
+    return default_smallk_cfg(prec);
+}
+
+static int tuned_ksg_pw(corr_ctx* ctx, int M, int k) {
+    for (const corr_tune_rec& r : ctx->tune)
+        if (r.kind == 1 && r.K == M && r.prec == k) return r.cfg;
+    return 0;
+}
+
+static void tune_store(corr_ctx* ctx, const corr_tune_rec& rec) {
+    for (corr_tune_rec& r : ctx->tune)
+        if (r.kind == rec.kind && r.K == rec.K && r.prec == rec.prec && r.na == rec.na && r.nb == rec.nb) {
+            r = rec;
+            return;
+        }
+    ctx->tune.push_back(rec);
+}
+
+// Exhaustive Pearson region maximum: standardise both regions into the
+// contraction layout, run the fused MFMA contraction, decode the key.
+// cfg < 0 selects the tuned (or default) small-K configuration.
+static int pearson_exhaustive(corr_ctx* ctx, const corr_field& A, const Box& ba, const corr_field& B, const Box& bb,
+                              bool sf, int prec, int cfg, corr_max* out, hipStream_t s) {
+    const int64_t na = ba.count(), nb = bb.count();
+    const bool acc64 = stats_acc64(CORR_PEARSON, A.M);
+    const int fmt = zfmt_for_prec(prec);
+    const bool small = A.M <= 128;
+    int64_t K, row_pad, col_pad;
+    if (small) {
+        K = smallk_pad_K(A.M);
+        if (cfg < 0) cfg = tuned_smallk_cfg(ctx, (int)K, prec, na, nb);
+        if (!smallk_config_ok(prec, cfg)) return fail(CORR_EINVAL, "tile configuration not valid for this precision");
+        row_pad = smallk_row_pad(cfg);
+        col_pad = smallk_col_pad(cfg);
+    } else {
+        K = round_up(A.M, gemm_k_pad(prec));
+        row_pad = gemm_row_pad();
+        col_pad = gemm_col_pad();
+    }
+    const int64_t na_pad = round_up(na, row_pad), nb_pad = round_up(nb, col_pad);
+    void *ah, *al, *bh, *bl;
+    int rc = launch_fill_u64(ctx->keys, 2, 0ull, s);
+    if (rc) return rc;
+    rc = standardize_box(ctx, A, ba, acc64, fmt, na_pad, K, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
+    if (rc) return rc;
+    rc = standardize_box(ctx, B, bb, acc64, fmt, nb_pad, K, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
+    if (rc) return rc;
+    const int32_t* self_col = nullptr;
+    int64_t n_self = 0;
+    if (sf && boxes_overlap(ba, bb)) {
+        void* m = nullptr;
+        rc = ws_get(ctx, WS_MISC, sizeof(int32_t) * (size_t)na, s, &m);
+        if (rc) return rc;
+        self_col_kernel<<<dim3((unsigned)((na + 255) / 256)), 256, 0, s>>>(ba, bb, (int32_t*)m);
+        CORR_LAUNCH_CHECK();
+        self_col = (const int32_t*)m;
+        n_self = overlap_count(ba, bb);
+    }
+    GemmArgs g{};
+    g.prec = prec;
+    g.a_hi = ah; g.a_lo = al; g.b_hi = bh; g.b_lo = bl;
+    g.K = K;
+    g.na = na; g.nb = nb; g.na_pad = na_pad; g.nb_pad = nb_pad;
+    g.self_col = self_col;
+    g.key = ctx->keys;
+    timing_begin(ctx, TK_GEMM, s);
+    rc = small ? launch_gemm_smallk(g, cfg, ctx->num_cus, s) : launch_gemm_max(g, ctx->num_cus, s);
+    timing_end(ctx, TK_GEMM, s);
+    if (rc) return rc;
+    unsigned long long k0, k1;
+    if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
+    decode_key(k0, ba, bb, true, out);
+    out->n_evaluated = na * nb - n_self;
+    return CORR_OK;
 }
 
 }  // namespace corr
@@ -214,6 +313,10 @@ int corr_create(int device, corr_ctx** out) {
     delete[] h;
     if (e == hipSuccess) e = hipMalloc(&c->keys, 64 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc(&c->keys_host, 64 * sizeof(unsigned long long), hipHostMallocDefault);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        e = hipEventCreate(&c->ev_start[i]);
+        if (e == hipSuccess) e = hipEventCreate(&c->ev_stop[i]);
+    }
     if (e != hipSuccess) {
         corr_destroy(c);
         return fail(CORR_EHIP, std::string("corr_create: ") + hipGetErrorString(e));
@@ -231,7 +334,165 @@ void corr_destroy(corr_ctx* c) {
     if (c->psi) (void)hipFree(c->psi);
     if (c->keys) (void)hipFree(c->keys);
     if (c->keys_host) (void)hipHostFree(c->keys_host);
+    for (int i = 0; i < 4; ++i) {
+        if (c->ev_start[i]) (void)hipEventDestroy(c->ev_start[i]);
+        if (c->ev_stop[i]) (void)hipEventDestroy(c->ev_stop[i]);
+    }
     delete c;
+}
+
+int corr_set_timing(corr_ctx* ctx, int on) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    ctx->timing = on != 0;
+    return CORR_OK;
+}
+
+int corr_kernel_time_ms(corr_ctx* ctx, int which, float* ms) {
+    if (!ctx || !ms) return fail(CORR_EINVAL, "null argument");
+    if (which < 0 || which > 3) return fail(CORR_EINVAL, "unknown kernel class");
+    *ms = -1.0f;
+    if (!ctx->ev_valid[which]) return CORR_OK;
+    CORR_HIP(hipEventSynchronize(ctx->ev_stop[which]));
+    CORR_HIP(hipEventElapsedTime(ms, ctx->ev_start[which], ctx->ev_stop[which]));
+    return CORR_OK;
+}
+
+int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                  const corr_region* rb, int prec, int reps, int* best_cfg, float* best_ms, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if ((rc = check_region(ra, *A, "ra"))) return rc;
+    if ((rc = check_region(rb, *B, "rb"))) return rc;
+    if (prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3) return fail(CORR_EUNSUPPORTED, "unknown precision");
+    if (reps < 1) return fail(CORR_EINVAL, "reps < 1");
+    if (best_cfg) *best_cfg = -1;
+    if (best_ms) *best_ms = -1.0f;
+    if (A->M > 128) return CORR_OK;  // the chunked contraction has a single configuration
+    hipStream_t s = (hipStream_t)stream;
+    Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
+    if (ba.count() * bb.count() >= (int64_t(1) << 31))
+        return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
+    const bool sf = same_field(*A, *B);
+    const bool saved_timing = ctx->timing;
+    ctx->timing = true;
+    int best = -1;
+    float best_t = 0.0f;
+    std::vector<float> t(reps);
+    for (int cfg = 0; cfg < smallk_num_configs(); ++cfg) {
+        if (!smallk_config_ok(prec, cfg)) continue;
+        corr_max tmp;
+        rc = pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);  // warm-up
+        for (int r = 0; r < reps && rc == CORR_OK; ++r) {
+            rc = pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);
+            if (rc == CORR_OK) rc = corr_kernel_time_ms(ctx, TK_GEMM, &t[r]);
+        }
+        if (rc) {
+            ctx->timing = saved_timing;
+            return rc;
+        }
+        std::sort(t.begin(), t.end());
+        float med = t[reps / 2];
+        if (best < 0 || med < best_t) {
+            best = cfg;
+            best_t = med;
+        }
+    }
+    ctx->timing = saved_timing;
+    tune_store(ctx, {0, smallk_pad_K(A->M), prec, ba.count(), bb.count(), best, best_t});
+    if (best_cfg) *best_cfg = best;
+    if (best_ms) *best_ms = best_t;
+    return CORR_OK;
+}
+
+int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
+                      int32_t k, int reps, int* best_pw, float* best_ms, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (reps < 1) return fail(CORR_EINVAL, "reps < 1");
+    if (best_pw) *best_pw = -1;
+    if (best_ms) *best_ms = -1.0f;
+    if (n <= 0) return fail(CORR_EINVAL, "autotuning needs a non-empty pair list");
+    if (!A) return fail(CORR_EINVAL, "A: null field");
+    std::vector<float> out_host;  // unused; results go to a workspace
+    void* mi = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ws_get(ctx, WS_PAIRS, sizeof(float) * (size_t)n, s, &mi);
+    if (rc) return rc;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = true;
+    int best = -1;
+    float best_t = 0.0f;
+    std::vector<float> t(reps);
+    static const int cands[] = {1, 2, 4, 8, 16};
+    // remove any previous choice so each candidate runs as given
+    for (size_t i = 0; i < ctx->tune.size(); ++i)
+        if (ctx->tune[i].kind == 1 && ctx->tune[i].K == A->M && ctx->tune[i].prec == k) {
+            ctx->tune.erase(ctx->tune.begin() + i);
+            break;
+        }
+    for (int pw : cands) {
+        if (ksg_lds_bytes(A->M, pw) > 160 * 1024) continue;
+        tune_store(ctx, {1, A->M, k, 0, 0, pw, 0.0f});
+        rc = corr_ksg_mi_pairs(ctx, A, B, pairs, n, k, 0, (float*)mi, nullptr, stream);  // warm-up
+        for (int r = 0; r < reps && rc == CORR_OK; ++r) {
+            rc = corr_ksg_mi_pairs(ctx, A, B, pairs, n, k, 0, (float*)mi, nullptr, stream);
+            if (rc == CORR_OK) rc = corr_kernel_time_ms(ctx, TK_KSG, &t[r]);
+        }
+        if (rc) break;
+        std::sort(t.begin(), t.end());
+        if (best < 0 || t[reps / 2] < best_t) {
+            best = pw;
+            best_t = t[reps / 2];
+        }
+    }
+    ctx->timing = saved_timing;
+    if (rc) return rc;
+    tune_store(ctx, {1, A->M, k, 0, 0, best, best_t});
+    CORR_HIP(hipStreamSynchronize(s));
+    if (best_pw) *best_pw = best;
+    if (best_ms) *best_ms = best_t;
+    return CORR_OK;
+}
+
+int corr_tune_save(corr_ctx* ctx, const char* path) {
+    if (!ctx || !path) return fail(CORR_EINVAL, "null argument");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(CORR_EINVAL, std::string("cannot write ") + path);
+    for (const corr_tune_rec& r : ctx->tune)
+        fprintf(f,
+                "{\"arch\": \"gfx950\", \"kind\": %d, \"K\": %d, \"prec\": %d, \"na\": %lld, \"nb\": %lld, "
+                "\"cfg\": %d, \"ms\": %.6f}\n",
+                r.kind, r.K, r.prec, (long long)r.na, (long long)r.nb, r.cfg, r.ms);
+    fclose(f);
+    return CORR_OK;
+}
+
+int corr_tune_load(corr_ctx* ctx, const char* path) {
+    if (!ctx || !path) return fail(CORR_EINVAL, "null argument");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(CORR_EINVAL, std::string("cannot read ") + path);
+    char line[512];
+    int n = 0;
+    while (fgets(line, sizeof line, f)) {
+        corr_tune_rec r{};
+        long long na = 0, nb = 0;
+        if (sscanf(line,
+                   " {\"arch\": \"gfx950\", \"kind\": %d, \"K\": %d, \"prec\": %d, \"na\": %lld, \"nb\": %lld, "
+                   "\"cfg\": %d, \"ms\": %f}",
+                   &r.kind, &r.K, &r.prec, &na, &nb, &r.cfg, &r.ms) != 7)
+            continue;
+        r.na = na;
+        r.nb = nb;
+        if (r.kind == 0 && !smallk_config_ok(r.prec, r.cfg)) continue;
+        if (r.kind == 1 && (r.cfg < 1 || r.cfg > 16 || r.K < 2 || ksg_lds_bytes(r.K, r.cfg) > 160 * 1024)) continue;
+        if (r.kind != 0 && r.kind != 1) continue;
+        tune_store(ctx, r);
+        ++n;
+    }
+    fclose(f);
+    return CORR_OK;
 }
 
 int corr_standardize(corr_ctx* ctx, const corr_field* A, float* mu32, float* inv32, float* sigma,
@@ -281,7 +542,10 @@ int corr_pearson_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, 
                              nullptr, &bh, &bl);
         if (rc) return rc;
     }
-    return launch_pearson_pairs(prec, ah, al, bh, bl, ld, pairs, n, r_out, ba, bb, 0, nullptr, s);
+    timing_begin(ctx, TK_PAIRS, s);
+    rc = launch_pearson_pairs(prec, ah, al, bh, bl, ld, pairs, n, r_out, ba, bb, 0, nullptr, s);
+    timing_end(ctx, TK_PAIRS, s);
+    return rc;
 }
 
 int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
@@ -315,9 +579,21 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
                              &unused);
         if (rc) return rc;
     }
+    void *sra, *srb;
+    rc = sorted_rows(ctx, (const float*)za, ld, ba.count(), A->M, WS_SORT_A, s, &sra);
+    if (rc) return rc;
+    if (zb == za) {
+        srb = sra;
+    } else {
+        rc = sorted_rows(ctx, (const float*)zb, ld, bb.count(), A->M, WS_SORT_B, s, &srb);
+        if (rc) return rc;
+    }
     KsgArgs a{};
     a.za = (const float*)za;
     a.zb = (const float*)zb;
+    a.sa = (const float*)sra;
+    a.sb = (const float*)srb;
+    a.pw = tuned_ksg_pw(ctx, A->M, k);
     a.ld = ld;
     a.inv_a = raw ? nullptr : sa.inv32;
     a.inv_b = raw ? nullptr : sb.inv32;
@@ -332,7 +608,10 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     a.ba = ba;
     a.bb = bb;
     a.same_field = 0;
-    return launch_ksg(a, ctx->num_cus, s);
+    timing_begin(ctx, TK_KSG, s);
+    rc = launch_ksg(a, ctx->num_cus, s);
+    timing_end(ctx, TK_KSG, s);
+    return rc;
 }
 
 int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
@@ -373,48 +652,16 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
         const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
         const int fmt = zfmt_for_prec(prec);
         void *ah, *al, *bh, *bl;
-        if (exhaustive) {
-            const int64_t K = round_up(A->M, gemm_k_pad(prec));
-            const int64_t na_pad = round_up(na, gemm_row_pad()), nb_pad = round_up(nb, gemm_col_pad());
-            rc = standardize_box(ctx, *A, ba, acc64, fmt, na_pad, K, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah,
-                                 &al);
-            if (rc) return rc;
-            rc = standardize_box(ctx, *B, bb, acc64, fmt, nb_pad, K, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh,
-                                 &bl);
-            if (rc) return rc;
-            const int32_t* self_col = nullptr;
-            int64_t n_self = 0;
-            if (sf && boxes_overlap(ba, bb)) {
-                void* m = nullptr;
-                rc = ws_get(ctx, WS_MISC, sizeof(int32_t) * (size_t)na, s, &m);
-                if (rc) return rc;
-                self_col_kernel<<<dim3((unsigned)((na + 255) / 256)), 256, 0, s>>>(ba, bb, (int32_t*)m);
-                CORR_LAUNCH_CHECK();
-                self_col = (const int32_t*)m;
-                n_self = overlap_count(ba, bb);
-            }
-            GemmArgs g{};
-            g.prec = prec;
-            g.a_hi = ah; g.a_lo = al; g.b_hi = bh; g.b_lo = bl;
-            g.K = K;
-            g.na = na; g.nb = nb; g.na_pad = na_pad; g.nb_pad = nb_pad;
-            g.self_col = self_col;
-            g.key = ctx->keys;
-            rc = launch_gemm_max(g, ctx->num_cus, s);
-            if (rc) return rc;
-            unsigned long long k0, k1;
-            if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
-            decode_key(k0, ba, bb, true, out);
-            out->n_evaluated = na * nb - n_self;
-            return CORR_OK;
-        }
+        if (exhaustive) return pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, -1, out, s);
         const int64_t ld = round_up(A->M, 16);
         rc = standardize_box(ctx, *A, ba, acc64, fmt, na, ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
         if (rc) return rc;
         rc = standardize_box(ctx, *B, bb, acc64, fmt, nb, ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
         if (rc) return rc;
+        timing_begin(ctx, TK_PAIRS, s);
         rc = launch_pearson_pairs(prec, ah, al, bh, bl, ld, sample_pairs, n_samples, nullptr, ba, bb, sf ? 1 : 0,
                                   ctx->keys, s);
+        timing_end(ctx, TK_PAIRS, s);
         if (rc) return rc;
         unsigned long long k0, k1;
         if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;
@@ -431,9 +678,17 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     if (rc) return rc;
     rc = standardize_box(ctx, *B, bb, true, ZF_KSG, nb, ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb, &unused);
     if (rc) return rc;
+    void *sra, *srb;
+    rc = sorted_rows(ctx, (const float*)za, ld, na, A->M, WS_SORT_A, s, &sra);
+    if (rc) return rc;
+    rc = sorted_rows(ctx, (const float*)zb, ld, nb, A->M, WS_SORT_B, s, &srb);
+    if (rc) return rc;
     KsgArgs a{};
     a.za = (const float*)za;
     a.zb = (const float*)zb;
+    a.sa = (const float*)sra;
+    a.sb = (const float*)srb;
+    a.pw = tuned_ksg_pw(ctx, A->M, k);
     a.ld = ld;
     a.inv_a = sa.inv32;
     a.inv_b = sb.inv32;
@@ -446,7 +701,9 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     a.ba = ba;
     a.bb = bb;
     a.same_field = sf ? 1 : 0;
+    timing_begin(ctx, TK_KSG, s);
     rc = launch_ksg(a, ctx->num_cus, s);
+    timing_end(ctx, TK_KSG, s);
     if (rc) return rc;
     unsigned long long k0, k1;
     if ((rc = read_keys(ctx, s, &k0, &k1))) return rc;

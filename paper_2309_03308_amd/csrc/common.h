@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/corr.h"
 
@@ -53,13 +54,26 @@ struct Box {
 // ---- workspace --------------------------------------------------------------
 enum WsSlot {
     WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
-    WS_PAIRS, WS_MISC, WS_COUNT
+    WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_COUNT
 };
 
 }  // namespace corr
 
+// One autotuner record. kind 0: fastest small-K tile configuration of the
+// exhaustive Pearson contraction for (K, prec, na, nb). kind 1: fastest KSG
+// pairs-per-wave mapping for (K = M, prec = k); na = nb = 0.
+struct corr_tune_rec {
+    int kind;
+    int K;
+    int prec;
+    int64_t na, nb;
+    int cfg;
+    float ms;
+};
+
 struct corr_ctx {
     int device = 0;
+    std::vector<corr_tune_rec> tune;
     int num_cus = 256;
     double* psi = nullptr;   // device psi(n), n = 0..psi_max (psi[0] unused)
     int psi_max = 0;
@@ -67,6 +81,11 @@ struct corr_ctx {
     size_t ws_size[corr::WS_COUNT] = {};
     unsigned long long* keys = nullptr;     // device scratch for max keys
     unsigned long long* keys_host = nullptr;  // pinned host mirror
+    // kernel timing hook: events per kernel class (see corr_set_timing)
+    bool timing = false;
+    hipEvent_t ev_start[4] = {};
+    hipEvent_t ev_stop[4] = {};
+    bool ev_valid[4] = {};
 };
 
 namespace corr {
@@ -124,8 +143,15 @@ struct KsgArgs {
     unsigned long long* key;  // may be NULL: fused region max
     Box ba, bb;            // rows of za/zb are the boxes' local indices
     int same_field;        // skip pA == pB
+    const float* sa;       // rows of za / zb sorted ascending, row stride ksg_p2(M), +inf padded
+    const float* sb;
+    int pw;                // pairs per wave chunk (<= 0: default)
 };
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s);
+int ksg_p2(int M);
+int ksg_default_pw(int M);
+size_t ksg_lds_bytes(int M, int pw);
+int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* out, int num_cus, hipStream_t s);
 
 // gemm.hip
 struct GemmArgs {
@@ -139,6 +165,22 @@ struct GemmArgs {
     unsigned long long* key;
 };
 int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s);
+int gemm_row_pad();
+int gemm_col_pad();
+int gemm_k_pad(int prec);
+
+// gemm_smallk.hip (members padded to K <= 128; A fragments held in registers)
+int launch_gemm_smallk(const GemmArgs& g, int cfg, int num_cus, hipStream_t s);
+int smallk_num_configs();
+int smallk_row_pad(int cfg);
+int smallk_col_pad(int cfg);
+int smallk_pad_K(int M);
+bool smallk_config_ok(int prec, int cfg);
+
+// timing hook helpers (api.hip): bracket a launch with events when enabled
+enum TimedKernel { TK_GEMM = 0, TK_KSG = 1, TK_PAIRS = 2, TK_STD = 3 };
+void timing_begin(corr_ctx* ctx, int which, hipStream_t s);
+void timing_end(corr_ctx* ctx, int which, hipStream_t s);
 
 // small utility kernels (api.hip)
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

@@ -7,8 +7,8 @@
 // R is never stored: each tile's epilogue folds |r| into a running maximum.
 //
 // Design (gfx950):
-//  - workgroup = 4 waves (2 x 2), workgroup tile 128 (A rows) x 256 (B rows),
-//    wave tile 64 x 128 = 2 x 4 blocks of v_mfma_f32_32x32x16_{f16,bf16}
+//  - workgroup = 4 waves (2 x 2), workgroup tile 128 (A rows) x 128 (B rows),
+//    wave tile 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x16_{f16,bf16}
 //    (v_mfma_f32_32x32x2_f32 for FP32 operands), FP32 accumulators;
 //  - K is consumed in chunks staged through LDS, double-buffered (global
 //    loads of chunk c+1 are in flight while chunk c is multiplied); LDS rows
@@ -29,8 +29,8 @@ typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
 
-constexpr int G_BM = 128, G_BN = 256;  // workgroup tile
-constexpr int G_WM = 2, G_WN = 4;      // 32x32 blocks per wave
+constexpr int G_BM = 128, G_BN = 128;  // workgroup tile
+constexpr int G_WM = 2, G_WN = 2;      // 32x32 blocks per wave
 constexpr int G_THREADS = 256;
 
 template <int PREC>
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
         const int ti = (int)(tile / n_tj), tj = (int)(tile % n_tj);
         const int64_t row0 = (int64_t)ti * G_BM, col0 = (int64_t)tj * G_BN;
 
-        // global -> register staging: A tile = 128 rows x 64 B = 512 x 16 B,
-        // B tile = 256 rows x 64 B = 1024 x 16 B (per part)
-        uint4 ra[T::PARTS][2], rb[T::PARTS][4];
+        // global -> register staging (per part): A tile = 128 rows x 64 B =
+        // 512 x 16 B, B tile = G_BN rows x 64 B
+        constexpr int NRB = G_BN * 4 / G_THREADS;
+        uint4 ra[T::PARTS][2], rb[T::PARTS][NRB];
         auto gload = [&](int c) {
             const int64_t kb = (int64_t)c * T::KC * T::ES;
 #pragma unroll
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
                     ra[q][r] = *reinterpret_cast<const uint4*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < NRB; ++r) {
                     int v = tid + G_THREADS * r;
                     rb[q][r] = *reinterpret_cast<const uint4*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
                 }
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
                     *reinterpret_cast<uint4*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < NRB; ++r) {
                     int v = tid + G_THREADS * r;
                     *reinterpret_cast<uint4*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
                 }
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
             if (c + 1 < n_chunks) gload(c + 1);
             const char* base = smem + stage * T::STAGE;
             const char* la_hi = base + (wr * 64 + (lane & 31)) * T::ROWB;
-            const char* lb_hi = base + G_BM * T::ROWB + (wc * 128 + (lane & 31)) * T::ROWB;
+            const char* lb_hi = base + G_BM * T::ROWB + (wc * 32 * G_WN + (lane & 31)) * T::ROWB;
             const int half = lane >> 5;
             if constexpr (T::F32) {
                 // 8 K-steps of 2 per chunk; lane reads k = 8q + 4*half + e
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
         auto elem_row = [&](int i, int r) -> int64_t {
             return row0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         };
-        auto elem_col = [&](int j) -> int64_t { return col0 + wc * 128 + j * 32 + (lane & 31); };
+        auto elem_col = [&](int j) -> int64_t { return col0 + wc * 32 * G_WN + j * 32 + (lane & 31); };
         float m = -1.0f;
         if (!edge && !self) {
 #pragma unroll

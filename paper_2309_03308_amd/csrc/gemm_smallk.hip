@@ -1,0 +1,292 @@
+// Exhaustive Pearson region maximum for small ensembles (K = padded member
+// count <= 128) as one MFMA contraction with the maximum fused (Sec. 3: the
+// brick-pair indicator is the maximum point-to-point correlation).
+//
+// R = Zhat_A Zhat_B^T is never stored. Design for gfx950 when K is small:
+//  - a workgroup (4 waves) keeps one B tile of BN standardised rows x K
+//    resident in LDS for its whole life (loaded once, one barrier);
+//  - every wave holds the complete A fragment of WM x 32 rows x K in
+//    registers (loaded straight from global memory, 16 bytes per lane per
+//    K-step), so A never touches LDS and the K loop has no barriers;
+//  - the wave sweeps the B tile in groups of WNG 32-column blocks:
+//    WM x WNG x K/16 MFMA (32x32x16 f16/bf16, or 32x32x2 f32 with a K
+//    permutation that lets one float4 read feed four steps) into FP32
+//    accumulators, then folds |r| of the group into its running maximum;
+//  - workgroups are (B tile, slice of A blocks); a wave walks the A blocks of
+//    its workgroup's slice, so LDS traffic is B only and HBM/L2 traffic is
+//    one pass over A per B tile.
+// The epilogue is the same as the chunked kernel: per-lane max of |r|, wave
+// max by shuffles, element search only when a group reaches the wave's best,
+// one 64-bit atomicMax per wave.
+#include "common.h"
+
+namespace corr {
+
+typedef _Float16 sk_h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 sk_b8 __attribute__((ext_vector_type(8)));
+typedef float sk_f16 __attribute__((ext_vector_type(16)));
+
+template <int PREC>
+struct SkT {
+    static constexpr bool F32 = PREC == CORR_PREC_F32;
+    static constexpr bool SPLIT = PREC == CORR_PREC_F16X3 || PREC == CORR_PREC_BF16X3;
+    static constexpr bool BF = PREC == CORR_PREC_BF16 || PREC == CORR_PREC_BF16X3;
+    static constexpr int ES = F32 ? 4 : 2;
+};
+
+__device__ __forceinline__ float sk_wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
+template <int PREC, int KV, int WM, int WNG, int BN>
+__global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_ablk_per_wg, int n_tj) {
+    using T = SkT<PREC>;
+    constexpr int PARTS = T::SPLIT ? 2 : 1;
+    constexpr int ROWB = KV * 16 + 16;  // padded LDS row bytes (conflict-free 16-byte reads)
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    // XCD-grouped order: blocks are dealt round-robin to 8 XCDs; give the
+    // blocks of one XCD consecutive logical ids so they share B tiles.
+    const int G = gridDim.x, b = blockIdx.x;
+    const int lg = (G % 8 == 0) ? ((b % 8) * (G / 8) + b / 8) : b;
+    const int tj = lg % n_tj, slice = lg / n_tj;
+    const int64_t col0 = (int64_t)tj * BN;
+    const int64_t rowb_g = (int64_t)KV * 16;
+
+    // ---- load the B tile (all parts) into LDS once
+    {
+        constexpr int NV = BN * KV;  // 16-byte vectors per part
+#pragma unroll
+        for (int q = 0; q < PARTS; ++q) {
+            const char* src = (const char*)(q ? g.b_lo : g.b_hi) + col0 * rowb_g;
+            char* dst = smem + q * BN * ROWB;
+            for (int v = tid; v < NV; v += 256) {
+                int row = v / KV, c = v - row * KV;
+                *reinterpret_cast<uint4*>(dst + row * ROWB + c * 16) =
+                    *reinterpret_cast<const uint4*>(src + row * rowb_g + c * 16);
+            }
+        }
+    }
+    __syncthreads();
+
+    const int64_t n_ablk = g.na_pad / (32 * WM);
+    const int64_t ab_begin = (int64_t)slice * n_ablk_per_wg;
+    int64_t ab_end = ab_begin + n_ablk_per_wg;
+    if (ab_end > n_ablk) ab_end = n_ablk;
+
+    float best = -1.0f;
+    unsigned long long best_key = 0;
+    const bool self = g.self_col != nullptr;
+    const int32_t nb = (int32_t)g.nb;
+
+    for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
+        const int64_t row0 = ab * 32 * WM;
+        // A fragment in registers: av[part][i][vector]
+        uint4 av[PARTS][WM][KV / 2];
+#pragma unroll
+        for (int q = 0; q < PARTS; ++q)
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                const char* src = (const char*)(q ? g.a_lo : g.a_hi) + (row0 + i * 32 + l32) * rowb_g;
+#pragma unroll
+                for (int s = 0; s < KV / 2; ++s)
+                    av[q][i][s] = *reinterpret_cast<const uint4*>(src + (2 * s + half) * 16);
+            }
+        const bool edge_rows = row0 + 32 * WM > g.na;
+
+        for (int jg = 0; jg < BN / 32; jg += WNG) {
+            sk_f16 acc[WM][WNG];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WNG; ++j) acc[i][j] = sk_f16{};
+#pragma unroll
+            for (int s = 0; s < KV / 2; ++s) {
+#pragma unroll
+                for (int j = 0; j < WNG; ++j) {
+                    const char* lb = smem + ((jg + j) * 32 + l32) * ROWB + (2 * s + half) * 16;
+                    uint4 bh = *reinterpret_cast<const uint4*>(lb);
+                    uint4 bl;
+                    if constexpr (T::SPLIT) bl = *reinterpret_cast<const uint4*>(lb + BN * ROWB);
+#pragma unroll
+                    for (int i = 0; i < WM; ++i) {
+                        if constexpr (T::F32) {
+                            const float* fa = reinterpret_cast<const float*>(&av[0][i][s]);
+                            const float* fb = reinterpret_cast<const float*>(&bh);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[e], fb[e], acc[i][j], 0, 0, 0);
+                        } else if constexpr (T::BF) {
+                            sk_b8 a8 = *reinterpret_cast<const sk_b8*>(&av[0][i][s]);
+                            sk_b8 b8 = *reinterpret_cast<const sk_b8*>(&bh);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8, acc[i][j], 0, 0, 0);
+                            if constexpr (T::SPLIT) {
+                                sk_b8 a8l = *reinterpret_cast<const sk_b8*>(&av[PARTS - 1][i][s]);
+                                sk_b8 b8l = *reinterpret_cast<const sk_b8*>(&bl);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8l, acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8l, b8, acc[i][j], 0, 0, 0);
+                            }
+                        } else {
+                            sk_h8 a8 = *reinterpret_cast<const sk_h8*>(&av[0][i][s]);
+                            sk_h8 b8 = *reinterpret_cast<const sk_h8*>(&bh);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[i][j], 0, 0, 0);
+                            if constexpr (T::SPLIT) {
+                                sk_h8 a8l = *reinterpret_cast<const sk_h8*>(&av[PARTS - 1][i][s]);
+                                sk_h8 b8l = *reinterpret_cast<const sk_h8*>(&bl);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8l, acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8l, b8, acc[i][j], 0, 0, 0);
+                            }
+                        }
+                    }
+                }
+            }
+            // ---- epilogue for this 32*WM x 32*WNG group
+            const int32_t c0 = (int32_t)(col0 + jg * 32);
+            const bool edge = edge_rows || (c0 + 32 * WNG > nb);
+            float m = -1.0f;
+            if (!edge && !self) {
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; r += 2)
+                            m = fmaxf(m, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
+            } else {
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            int32_t col = c0 + j * 32 + l32;
+                            bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
+                            if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
+                        }
+            }
+            const float wm = sk_wave_max(m);
+            if (wm >= 0.0f && wm >= best) {
+                uint32_t cand = 0xffffffffu, neg = 0;
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            // 32x32 accumulator layout: register r of lane l holds
+                            // row 8*(r/4) + 4*(l/32) + r%4, column l%32
+                            int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            int32_t col = c0 + j * 32 + l32;
+                            float v = acc[i][j][r];
+                            bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
+                            uint32_t lin = (uint32_t)row * (uint32_t)nb + (uint32_t)col;
+                            if (ok && fabsf(v) == wm && lin < cand) {
+                                cand = lin;
+                                neg = v < 0.0f ? 1u : 0u;
+                            }
+                        }
+                unsigned long long k = (cand == 0xffffffffu) ? 0ull : make_key(wm, cand, neg);
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    unsigned long long o = __shfl_xor(k, off, 64);
+                    k = o > k ? o : k;
+                }
+                best_key = k > best_key ? k : best_key;
+                best = wm;
+            }
+        }
+    }
+    if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
+}
+
+// ---------------------------------------------------------------- dispatch
+struct SkCfg {
+    int wm, wng, bn;
+};
+
+template <int PREC, int KV, int WM, int WNG, int BN>
+static int launch_sk_t(const GemmArgs& g, int num_cus, int wg_per_cu, hipStream_t s) {
+    constexpr int PARTS = SkT<PREC>::SPLIT ? 2 : 1;
+    constexpr int ROWB = KV * 16 + 16;
+    const size_t lds = (size_t)PARTS * BN * ROWB;
+    const int n_tj = (int)(g.nb_pad / BN);
+    const int64_t n_ablk = g.na_pad / (32 * WM);
+    // slices per B tile so that the grid holds about wg_per_cu workgroups per CU
+    int64_t want = (int64_t)num_cus * wg_per_cu;
+    int64_t slices = (want + n_tj - 1) / n_tj;
+    if (slices < 1) slices = 1;
+    if (slices > n_ablk) slices = n_ablk;
+    int64_t per = (n_ablk + slices - 1) / slices;
+    per = (per + 3) / 4 * 4;  // whole rounds of the 4 waves
+    slices = (n_ablk + per - 1) / per;
+    const int64_t grid = slices * n_tj;
+    static bool attr = false;
+    if (!attr) {
+        CORR_HIP(hipFuncSetAttribute((const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    gemm_smallk_kernel<PREC, KV, WM, WNG, BN><<<dim3((unsigned)grid), 256, lds, s>>>(g, (int)per, n_tj);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+// Small-K contraction K values: members are zero-padded to 64, 112 or 128.
+int smallk_pad_K(int M) { return M <= 64 ? 64 : (M <= 112 ? 112 : 128); }
+
+template <int PREC, int WM, int WNG, int BN>
+static int launch_sk_k(const GemmArgs& g, int num_cus, int wg_per_cu, hipStream_t s) {
+    constexpr int ES = SkT<PREC>::ES;
+    switch (g.K) {
+        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
+        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
+        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
+    }
+    return fail(CORR_EUNSUPPORTED, "small-K contraction: K must be 64, 112 or 128");
+}
+
+// Tile configurations the autotuner chooses from (index = config id):
+// {row blocks of 32 per wave, column blocks of 32 per group, B tile rows}.
+static const SkCfg kSkCfgs[] = {{2, 2, 256}, {1, 4, 256}, {2, 2, 128}, {1, 2, 128}};
+constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
+
+template <int PREC>
+static int launch_sk_p(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {
+    constexpr bool SPLIT = SkT<PREC>::SPLIT;
+    switch (cfg) {
+        case 0: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 256>(g, num_cus, 2, s); break;
+        case 1: return launch_sk_k<PREC, 1, 4, 256>(g, num_cus, 2, s);
+        case 2: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 128>(g, num_cus, 2, s); break;
+        case 3: return launch_sk_k<PREC, 1, 2, 128>(g, num_cus, 2, s);
+    }
+    return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
+}
+
+int smallk_num_configs() { return kNumSkCfgs; }
+int smallk_row_pad(int cfg) { return 32 * kSkCfgs[cfg].wm; }
+int smallk_col_pad(int cfg) { return kSkCfgs[cfg].bn; }
+// split modes keep hi and lo A fragments; only one-row-block configs fit
+bool smallk_config_ok(int prec, int cfg) {
+    return cfg >= 0 && cfg < kNumSkCfgs && (!prec_split(prec) || kSkCfgs[cfg].wm == 1);
+}
+
+int launch_gemm_smallk(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {
+    if (g.na == 0 || g.nb == 0) return CORR_OK;
+    if (!smallk_config_ok(g.prec, cfg)) return fail(CORR_EINVAL, "small-K contraction: bad tile configuration");
+    switch (g.prec) {
+        case CORR_PREC_F32: return launch_sk_p<CORR_PREC_F32>(g, cfg, num_cus, s);
+        case CORR_PREC_F16: return launch_sk_p<CORR_PREC_F16>(g, cfg, num_cus, s);
+        case CORR_PREC_BF16: return launch_sk_p<CORR_PREC_BF16>(g, cfg, num_cus, s);
+        case CORR_PREC_F16X3: return launch_sk_p<CORR_PREC_F16X3>(g, cfg, num_cus, s);
+        case CORR_PREC_BF16X3: return launch_sk_p<CORR_PREC_BF16X3>(g, cfg, num_cus, s);
+    }
+    return fail(CORR_EUNSUPPORTED, "unknown precision");
+}
+
+}  // namespace corr

@@ -6,23 +6,29 @@
 // the j != i with marginal distance strictly below eps_i; the estimate is
 // psi(M) + psi(k) - mean_i[psi(n_x,i + 1) + psi(n_y,i + 1)].
 //
-// Design (gfx950, wave64):
-//  - one wave per pair; the pair's 2M samples are staged in the wave's own
-//    LDS slice interleaved as (x_j, y_j), so one ds_read_b128 broadcast
-//    serves two j for every lane;
-//  - lane = sample i (SLOTS samples per lane per sweep);
-//  - selection of eps_i keeps the KP1 >= k+1 smallest distances of ALL j
-//    (the self distance d_ii = 0 included) in registers; inserting d costs
-//    one v_min_f32 and KP1-1 v_med3_f32 that are independent of each other:
-//    new t[p] = med3(t[p-1], d, t[p]). The (k+1)-th smallest including the
-//    zero self distance is exactly the k-th smallest over j != i, with ties
-//    kept as a multiset;
-//  - the count sweep also includes j = i, which adds 1 exactly when
-//    eps_i > 0, and is corrected;
-//  - digamma at integers comes from an FP64 table; the per-lane sum and the
-//    wave reduction (shuffles) are FP64.
-// Distances are plain FP32 subtract/abs/max (no contraction), so the integer
-// counts are bit-reproducible against any IEEE FP32 evaluation.
+// Design (gfx950, wave64, VALU-bound):
+//  - a wave owns a chunk of PW consecutive pairs and stages, per pair, the
+//    joint samples interleaved as (x_j, y_j) (one ds_read_b128 serves two j)
+//    and both marginals sorted ascending (sorted once per point, not per
+//    pair, by sort_rows_kernel);
+//  - the chunk's PW*M (pair, sample) items are laid densely over the lanes,
+//    so no lane idles when M is not a multiple of 64; the j sweep reads the
+//    item's own pair slot (at most two pairs per 64 items when M >= 64, i.e.
+//    two LDS addresses per read);
+//  - eps_i: the KP1 >= k+1 smallest distances over ALL j (the self distance
+//    0 included) are kept in registers; inserting d is one v_min_f32 and
+//    KP1-1 mutually independent v_med3_f32: t[p] <- med3(t[p-1], d, t[p]).
+//    The (k+1)-th smallest including the zero self distance is exactly the
+//    k-th smallest over j != i, ties kept as a multiset;
+//  - n_x,i: since s -> fl32(x_i - s) is monotone, the j with
+//    |fl32(x_i - x_j)| < eps_i form one run of the sorted marginal; two
+//    branch-free binary searches find it (the run includes j = i exactly when
+//    eps_i > 0, which is subtracted). This replaces M distance tests with
+//    2 log2(M) probes and gives the same integer bit for bit;
+//  - each item's (n_x, n_y) is kept in LDS; one lane per pair then sums the
+//    FP64 digamma terms (integer-argument table) in sample order, so MI is
+//    deterministic.
+// Distances are plain FP32 subtract/abs/max (no contraction).
 #include "common.h"
 
 namespace corr {
@@ -36,180 +42,281 @@ __device__ __forceinline__ void topk_insert(float (&t)[KP1], float d) {
     t[0] = fminf(t[0], d);
 }
 
-template <int KP1, int SLOTS>
-__global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, int mpad2) {
-    extern __shared__ float4 lds_raw[];
+// number of leading entries s of the sorted row with fl32(x - s) >= eps
+// (first index of the run |x - s| < eps); p2 is a power of two > M, row
+// padded with +inf
+__device__ __forceinline__ int lower_run(const float* s, int p2, float x, float eps) {
+    int pos = 0;
+    for (int step = p2 >> 1; step >= 1; step >>= 1) {
+        float v = s[pos + step - 1];
+        pos += (x - v < eps) ? 0 : step;
+    }
+    return pos;
+}
+// number of leading entries with fl32(x - s) > -eps (end of the run)
+__device__ __forceinline__ int upper_run(const float* s, int p2, float x, float eps) {
+    int pos = 0;
+    for (int step = p2 >> 1; step >= 1; step >>= 1) {
+        float v = s[pos + step - 1];
+        pos += (x - v > -eps) ? step : 0;
+    }
+    return pos;
+}
+
+struct KsgLayout {
+    int mpad2;      // M rounded up to even (interleaved samples, float2 entries)
+    int p2;         // power of two >= M (sorted marginals)
+    int pw;         // pairs per wave chunk
+    int slot_f;     // floats per pair slot
+    int wave_f;     // floats per wave (slots + item terms as doubles)
+};
+
+template <int KP1>
+__global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L) {
+    extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float4* buf4 = lds_raw + wave * (mpad2 / 2);
-    float2* buf2 = reinterpret_cast<float2*>(buf4);
+    float* wbase = lds_f + wave * L.wave_f;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(wbase + L.pw * L.slot_f);  // packed n_x | n_y << 16
     const int M = a.M;
     const int k = a.k;
     const int64_t nb = a.bb.count();
     const float inf = __builtin_inff();
     unsigned long long best = 0;
     uint32_t n_in_max = 0;
+    const int64_t chunk_pairs = (int64_t)KSG_WAVES * L.pw;
 
-    for (int64_t base = (int64_t)blockIdx.x * KSG_WAVES; base < n_total;
-         base += (int64_t)gridDim.x * KSG_WAVES) {
-        const int64_t t = base + wave;
-        bool active = t < n_total;
-        int64_t la = -1, lb = -1;
-        bool in_max = false, zero = false;
-        if (active) {
-            if (a.pairs) {
-                int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
-                la = a.ba.local(ga);
-                lb = a.bb.local(gb);
-                in_max = a.key && !(a.same_field && ga == gb);
-            } else {
-                la = t / nb;
-                lb = t - la * nb;
-                int32_t ga = a.ba.global(la), gb = a.bb.global(lb);
-                if (a.same_field && ga == gb) active = false;
-                in_max = a.key != nullptr;
+    for (int64_t base = (int64_t)blockIdx.x * chunk_pairs; base < n_total; base += (int64_t)gridDim.x * chunk_pairs) {
+        const int64_t wbase_pair = base + (int64_t)wave * L.pw;
+        // ---- stage the wave's pairs (all waves reach every barrier)
+        for (int q = 0; q < L.pw; ++q) {
+            const int64_t t = wbase_pair + q;
+            float* slot = wbase + q * L.slot_f;
+            float2* xy = reinterpret_cast<float2*>(slot);
+            float* sx = slot + 2 * L.mpad2;
+            float* sy = sx + L.p2;
+            int64_t la = -1, lb = -1;
+            bool ok = false;
+            if (t < n_total) {
+                if (a.pairs) {
+                    la = a.ba.local(a.pairs[2 * t]);
+                    lb = a.bb.local(a.pairs[2 * t + 1]);
+                } else {
+                    la = t / nb;
+                    lb = t - la * nb;
+                }
+                ok = la >= 0 && lb >= 0;
+                if (ok && a.inv_a) ok = (a.inv_a[la] != 0.0f) && (a.inv_b[lb] != 0.0f);
             }
-            // rows are the boxes' local indices; a pair outside its box is
-            // not evaluated (MI = 0, zero counts, not in the max)
-            if (la < 0 || lb < 0) {
-                zero = true;
-                in_max = false;
-            } else if (active && a.inv_a) {
-                zero = (a.inv_a[la] == 0.0f) || (a.inv_b[lb] == 0.0f);
+            if (ok) {
+                const float* xa = a.za + la * a.ld;
+                const float* yb = a.zb + lb * a.ld;
+                const float* sxa = a.sa + la * L.p2;
+                const float* syb = a.sb + lb * L.p2;
+                for (int j = lane; j < L.mpad2; j += 64)
+                    xy[j] = (j < M) ? make_float2(xa[j], yb[j]) : make_float2(inf, inf);
+                for (int j = lane; j < L.p2; j += 64) {
+                    sx[j] = sxa[j];
+                    sy[j] = syb[j];
+                }
             }
-        }
-        const int64_t ra = la, rb = lb;
-        // stage the pair's samples (all waves reach the barrier below)
-        if (active && !zero) {
-            const float* xa = a.za + ra * a.ld;
-            const float* yb = a.zb + rb * a.ld;
-            for (int j = lane; j < mpad2; j += 64)
-                buf2[j] = (j < M) ? make_float2(xa[j], yb[j]) : make_float2(inf, inf);
         }
         __syncthreads();
-        if (active && !zero) {
-            double acc = 0.0;
-            for (int i0 = 0; i0 < M; i0 += 64 * SLOTS) {
-                float xi[SLOTS], yi[SLOTS], eps[SLOTS];
-                float tk[SLOTS][KP1];
+        // ---- items: u = q * M + i over the wave's pairs
+        const int n_items = L.pw * M;
+        for (int u0 = 0; u0 < n_items; u0 += 64) {
+            const int u = u0 + lane;
+            const int uc = u < n_items ? u : n_items - 1;
+            const int q = uc / M, i = uc - q * M;
+            const float* slot = wbase + q * L.slot_f;
+            const float4* xy4 = reinterpret_cast<const float4*>(slot);
+            const float2 me = reinterpret_cast<const float2*>(slot)[i];
+            float tk[KP1];
 #pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    int i = min(i0 + lane + 64 * s, M - 1);
-                    float2 v = buf2[i];
-                    xi[s] = v.x;
-                    yi[s] = v.y;
-#pragma unroll
-                    for (int p = 0; p < KP1; ++p) tk[s][p] = inf;
-                }
-                for (int j2 = 0; j2 < mpad2 / 2; ++j2) {
-                    float4 v = buf4[j2];
-#pragma unroll
-                    for (int s = 0; s < SLOTS; ++s) {
-                        float d0 = fmaxf(fabsf(xi[s] - v.x), fabsf(yi[s] - v.y));
-                        float d1 = fmaxf(fabsf(xi[s] - v.z), fabsf(yi[s] - v.w));
-                        topk_insert<KP1>(tk[s], d0);
-                        topk_insert<KP1>(tk[s], d1);
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    float e = tk[s][0];
-#pragma unroll
-                    for (int p = 1; p < KP1; ++p) e = (p == k) ? tk[s][p] : e;
-                    eps[s] = e;
-                }
-                int cx[SLOTS], cy[SLOTS];
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) cx[s] = cy[s] = 0;
-                for (int j2 = 0; j2 < mpad2 / 2; ++j2) {
-                    float4 v = buf4[j2];
-#pragma unroll
-                    for (int s = 0; s < SLOTS; ++s) {
-                        cx[s] += (fabsf(xi[s] - v.x) < eps[s]) ? 1 : 0;
-                        cy[s] += (fabsf(yi[s] - v.y) < eps[s]) ? 1 : 0;
-                        cx[s] += (fabsf(xi[s] - v.z) < eps[s]) ? 1 : 0;
-                        cy[s] += (fabsf(yi[s] - v.w) < eps[s]) ? 1 : 0;
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) {
-                    int i = i0 + lane + 64 * s;
-                    if (i < M) {
-                        int self = eps[s] > 0.0f ? 1 : 0;
-                        int nx = cx[s] - self, ny = cy[s] - self;
-                        acc += a.psi[nx + 1] + a.psi[ny + 1];
-                        if (a.counts_out) {
-                            int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M + i;
-                            *c = make_int2(nx, ny);
-                        }
-                    }
-                }
+            for (int p = 0; p < KP1; ++p) tk[p] = inf;
+            for (int j2 = 0; j2 < L.mpad2 / 2; ++j2) {
+                float4 v = xy4[j2];
+                float d0 = fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y));
+                float d1 = fmaxf(fabsf(me.x - v.z), fabsf(me.y - v.w));
+                topk_insert<KP1>(tk, d0);
+                topk_insert<KP1>(tk, d1);
             }
+            float eps = tk[0];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            float mi = (float)(a.psi[M] + a.psi[k] - acc / (double)M);
-            if (a.mi_out && lane == 0) a.mi_out[t] = mi;
-            if (in_max) {
-                unsigned long long key = make_key(mi, (uint32_t)(la * nb + lb), 0u);
-                best = key > best ? key : best;
-                ++n_in_max;
-            }
-        } else if (active && zero) {
-            if (a.mi_out && lane == 0) a.mi_out[t] = 0.0f;
-            if (a.counts_out) {
-                int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M;
-                for (int i = lane; i < M; i += 64) c[i] = make_int2(0, 0);
-            }
-            if (in_max) {
-                unsigned long long key = make_key(0.0f, (uint32_t)(la * nb + lb), 0u);
-                best = key > best ? key : best;
-                ++n_in_max;
+            for (int p = 1; p < KP1; ++p) eps = (p == k) ? tk[p] : eps;
+            const float* sx = slot + 2 * L.mpad2;
+            const float* sy = sx + L.p2;
+            const int self = eps > 0.0f ? 1 : 0;
+            int nx = upper_run(sx, L.p2, me.x, eps) - lower_run(sx, L.p2, me.x, eps) - self;
+            int ny = upper_run(sy, L.p2, me.y, eps) - lower_run(sy, L.p2, me.y, eps) - self;
+            nx = nx < 0 ? 0 : nx;
+            ny = ny < 0 ? 0 : ny;
+            if (u < n_items) {
+                cnt[u] = (uint32_t)nx | ((uint32_t)ny << 16);
+                const int64_t t = wbase_pair + q;
+                if (a.counts_out && t < n_total)
+                    reinterpret_cast<int2*>(a.counts_out)[t * M + i] = make_int2(nx, ny);
             }
         }
-        __syncthreads();  // the slice is rewritten by the next pair
+        __syncthreads();
+        // ---- per pair: one lane sums the M terms in sample order
+        if (lane < L.pw) {
+            const int q = lane;
+            const int64_t t = wbase_pair + q;
+            if (t < n_total) {
+                int64_t la, lb;
+                bool in_max = a.key != nullptr;
+                if (a.pairs) {
+                    int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
+                    la = a.ba.local(ga);
+                    lb = a.bb.local(gb);
+                    if (a.same_field && ga == gb) in_max = false;
+                } else {
+                    la = t / nb;
+                    lb = t - la * nb;
+                    if (a.same_field && a.ba.global(la) == a.bb.global(lb)) in_max = false;
+                }
+                bool ok = la >= 0 && lb >= 0;
+                if (!ok) in_max = false;
+                bool zero = ok && a.inv_a && ((a.inv_a[la] == 0.0f) || (a.inv_b[lb] == 0.0f));
+                float mi = 0.0f;
+                if (ok && !zero) {
+                    double acc = 0.0;
+                    const uint32_t* cq = cnt + q * M;
+                    for (int i = 0; i < M; ++i) {
+                        uint32_t c = cq[i];
+                        acc += a.psi[(c & 0xffffu) + 1] + a.psi[(c >> 16) + 1];
+                    }
+                    mi = (float)(a.psi[M] + a.psi[k] - acc / (double)M);
+                } else if (a.counts_out) {
+                    int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M;
+                    for (int i = 0; i < M; ++i) c[i] = make_int2(0, 0);
+                }
+                if (a.mi_out) a.mi_out[t] = mi;
+                if (in_max) {
+                    unsigned long long key = make_key(mi, (uint32_t)(la * nb + lb), 0u);
+                    best = key > best ? key : best;
+                    ++n_in_max;
+                }
+            }
+        }
+        __syncthreads();  // slots and terms are rewritten by the next chunk
     }
-    if (a.key && lane == 0 && n_in_max) {
-        atomicMax(a.key, best);
-        atomicAdd(a.key + 1, (unsigned long long)n_in_max);
+    if (a.key) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            unsigned long long o = __shfl_xor(best, off, 64);
+            best = o > best ? o : best;
+            n_in_max += __shfl_xor(n_in_max, off, 64);
+        }
+        if (lane == 0 && n_in_max) {
+            atomicMax(a.key, best);
+            atomicAdd(a.key + 1, (unsigned long long)n_in_max);
+        }
     }
 }
 
+// One wave per row: bitonic sort of the row's M values (padded to p2 with
+// +inf) in LDS, written to out[row * p2 ...].
+__global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict__ z, int64_t ld, int64_t nrows, int M,
+                                                        int p2, float* __restrict__ out) {
+    extern __shared__ float srt[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* s = srt + wave * p2;
+    for (int64_t r0 = (int64_t)blockIdx.x * 4; r0 < nrows; r0 += (int64_t)gridDim.x * 4) {
+        const int64_t r = r0 + wave;
+        const bool act = r < nrows;
+        for (int j = lane; j < p2; j += 64) s[j] = (act && j < M) ? z[r * ld + j] : __builtin_inff();
+        __syncthreads();
+        for (int size = 2; size <= p2; size <<= 1) {
+            for (int stride = size >> 1; stride >= 1; stride >>= 1) {
+                for (int e = lane; e < p2 / 2; e += 64) {
+                    int lo = 2 * e - (e & (stride - 1));
+                    int hi = lo + stride;
+                    bool asc = (lo & size) == 0;
+                    float x = s[lo], y = s[hi];
+                    if ((x > y) == asc) {
+                        s[lo] = y;
+                        s[hi] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (act)
+            for (int j = lane; j < p2; j += 64) out[r * p2 + j] = s[j];
+        __syncthreads();
+    }
+}
+
+// Sorted-row length: a power of two with at least one +inf sentinel after
+// the M values, so a run can reach the end of the row (the branch-free
+// searches return at most p2 - 1).
+int ksg_p2(int M) {
+    int p = 64;
+    while (p < M + 1) p <<= 1;
+    return p;
+}
+
+int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* out, int num_cus, hipStream_t s) {
+    if (nrows == 0) return CORR_OK;
+    const int p2 = ksg_p2(M);
+    int64_t blocks = (nrows + 3) / 4;
+    int64_t cap = (int64_t)num_cus * 8;
+    if (blocks > cap) blocks = cap;
+    sort_rows_kernel<<<dim3((unsigned)blocks), 256, 4 * p2 * sizeof(float), s>>>(z, ld, nrows, M, p2, out);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+// Pairs per wave chunk: dense items (pw * M close to a multiple of 64) traded
+// against LDS per wave (occupancy). pw <= 0 picks the default.
+int ksg_default_pw(int M) { return M >= 512 ? 1 : (M >= 192 ? 2 : (M >= 48 ? 4 : 16)); }
+
+static KsgLayout ksg_layout(int M, int pw) {
+    KsgLayout L;
+    L.mpad2 = (M + 1) & ~1;
+    L.p2 = ksg_p2(M);
+    L.pw = pw > 0 ? pw : ksg_default_pw(M);
+    L.slot_f = 2 * L.mpad2 + 2 * L.p2;
+    L.slot_f = (L.slot_f + 3) & ~3;
+    L.wave_f = L.pw * L.slot_f + L.pw * M;  // + packed counts per item
+    L.wave_f = (L.wave_f + 3) & ~3;
+    return L;
+}
+
+size_t ksg_lds_bytes(int M, int pw) { return (size_t)KSG_WAVES * ksg_layout(M, pw).wave_f * sizeof(float); }
+
 template <int KP1>
-static void launch_kp(const KsgArgs& a, int64_t n_total, int mpad2, int slots, dim3 grid, size_t lds,
-                      hipStream_t s) {
-    if (slots == 1)
-        ksg_kernel<KP1, 1><<<grid, 256, lds, s>>>(a, n_total, mpad2);
-    else if (slots == 2)
-        ksg_kernel<KP1, 2><<<grid, 256, lds, s>>>(a, n_total, mpad2);
-    else
-        ksg_kernel<KP1, 4><<<grid, 256, lds, s>>>(a, n_total, mpad2);
+static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, dim3 grid, size_t lds, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        CORR_HIP(hipFuncSetAttribute((const void*)ksg_kernel<KP1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+        attr = true;
+    }
+    ksg_kernel<KP1><<<grid, 256, lds, s>>>(a, n_total, L);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
 }
 
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     int64_t n_total = a.pairs ? a.n : a.ba.count() * a.bb.count();
     if (n_total == 0) return CORR_OK;
-    const int mpad2 = (a.M + 1) & ~1;
-    const size_t lds = (size_t)KSG_WAVES * mpad2 * sizeof(float2);
-    int slots = a.M <= 64 ? 1 : (a.M <= 128 ? 2 : 4);
-    int64_t blocks = (n_total + KSG_WAVES - 1) / KSG_WAVES;
+    const KsgLayout L = ksg_layout(a.M, a.pw);
+    const size_t lds = (size_t)KSG_WAVES * L.wave_f * sizeof(float);
+    if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
+    const int64_t chunk_pairs = (int64_t)KSG_WAVES * L.pw;
+    int64_t blocks = (n_total + chunk_pairs - 1) / chunk_pairs;
     int64_t cap = (int64_t)num_cus * 8;
     dim3 grid((unsigned)(blocks < cap ? blocks : cap));
     const int kp1 = a.k + 1;
-    if (kp1 == 11)
-        launch_kp<11>(a, n_total, mpad2, slots, grid, lds, s);
-    else if (kp1 <= 4)
-        launch_kp<4>(a, n_total, mpad2, slots, grid, lds, s);
-    else if (kp1 <= 8)
-        launch_kp<8>(a, n_total, mpad2, slots, grid, lds, s);
-    else if (kp1 <= 12)
-        launch_kp<12>(a, n_total, mpad2, slots, grid, lds, s);
-    else if (kp1 <= 16)
-        launch_kp<16>(a, n_total, mpad2, slots, grid, lds, s);
-    else if (kp1 <= 24)
-        launch_kp<24>(a, n_total, mpad2, slots, grid, lds, s);
-    else
-        launch_kp<32>(a, n_total, mpad2, slots, grid, lds, s);
-    CORR_LAUNCH_CHECK();
-    return CORR_OK;
+    if (kp1 == 11) return launch_kp<11>(a, n_total, L, grid, lds, s);
+    if (kp1 <= 4) return launch_kp<4>(a, n_total, L, grid, lds, s);
+    if (kp1 <= 8) return launch_kp<8>(a, n_total, L, grid, lds, s);
+    if (kp1 <= 12) return launch_kp<12>(a, n_total, L, grid, lds, s);
+    if (kp1 <= 16) return launch_kp<16>(a, n_total, L, grid, lds, s);
+    if (kp1 <= 24) return launch_kp<24>(a, n_total, L, grid, lds, s);
+    return launch_kp<32>(a, n_total, L, grid, lds, s);
 }
 
 }  // namespace corr

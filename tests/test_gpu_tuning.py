@@ -1,0 +1,86 @@
+"""Autotuner and tile configurations: every configuration computes the same
+thing (the MFMA K order and the KSG arithmetic do not depend on the tile
+shape or the pair mapping), and the tuning table round-trips through a file."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import __graft_entry__ as g
+    g._ensure_built()
+    import paper_2309_03308_amd as pc
+    e = synth.make_cfg2()
+    ctx = pc.Context(0)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    ra, rb = [pc.region(*r.as_tuple()) for r in e.regions]
+    yield dict(torch=torch, pc=pc, e=e, ctx=ctx, f=f, ra=ra, rb=rb)
+    ctx.close()
+
+
+def _force(ctx, tmp_path, recs):
+    p = os.path.join(str(tmp_path), "tune.jsonl")
+    with open(p, "w") as fh:
+        for r in recs:
+            fh.write(json.dumps(dict(arch="gfx950", **r)) + "\n")
+    ctx.corr_tune_load(p)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16", "f16x3", "f32"])
+def test_all_tile_configs_identical(env, tmp_path, prec):
+    ctx, f, ra, rb = env["ctx"], env["f"], env["ra"], env["rb"]
+    split = prec.endswith("x3")
+    outs = {}
+    for cfg in range(4):
+        if split and cfg in (0, 2):
+            continue
+        _force(ctx, tmp_path, [dict(kind=0, K=112, prec=env["pc"].PREC[prec], na=20480, nb=20480, cfg=cfg, ms=0.0)])
+        outs[cfg] = ctx.corr_region_max(f, ra, rb, "pearson", prec)
+        _say(f"  {prec} cfg {cfg}: {outs[cfg]}")
+    vals = list(outs.values())
+    assert all(v == vals[0] for v in vals)
+
+
+def test_autotune_and_roundtrip(env, tmp_path):
+    ctx, f, ra, rb, pc = env["ctx"], env["f"], env["ra"], env["rb"], env["pc"]
+    cfg, ms = ctx.corr_autotune(f, ra, rb, "f16", reps=3)
+    _say(f"  autotune f16 -> cfg {cfg} {ms:.4f} ms")
+    assert cfg in (0, 1, 2, 3) and ms > 0
+    p = os.path.join(str(tmp_path), "saved.jsonl")
+    ctx.corr_tune_save(p)
+    recs = [json.loads(l) for l in open(p)]
+    assert any(r["kind"] == 0 and r["cfg"] == cfg and r["na"] == 20480 for r in recs)
+    ctx2 = pc.Context(0)
+    ctx2.corr_tune_load(p)
+    assert ctx2.corr_region_max(f, ra, rb, "pearson", "f16") == ctx.corr_region_max(f, ra, rb, "pearson", "f16")
+    ctx2.close()
+
+
+def test_ksg_mappings_identical(env, tmp_path):
+    torch, ctx, f, e = env["torch"], env["ctx"], env["f"], env["e"]
+    pairs = torch.from_numpy(synth.region_pairs_uniform(31, 20011, e.regions[0], e.regions[1], e.nx, e.ny)).cuda()
+    ref = None
+    for pw in (1, 2, 4, 8, 16):
+        _force(ctx, tmp_path, [dict(kind=1, K=100, prec=10, na=0, nb=0, cfg=pw, ms=0.0)])
+        mi, cnt = ctx.corr_ksg_mi_pairs(f, pairs, k=10, counts=True)
+        got = (mi.cpu().numpy(), cnt.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), pw
+    pw, ms = ctx.corr_ksg_autotune(f, pairs, k=10, reps=2)
+    _say(f"  ksg autotune -> pw {pw} {ms:.3f} ms")
+    assert pw in (1, 2, 4, 8, 16) and ms > 0
