@@ -607,6 +607,8 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     a.key = nullptr;
     a.ba = ba;
     a.bb = bb;
+    a.whole_a = 1;
+    a.whole_b = 1;
     a.same_field = 0;
     timing_begin(ctx, TK_KSG, s);
     rc = launch_ksg(a, ctx->num_cus, s);
@@ -700,6 +702,8 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     a.key = ctx->keys;
     a.ba = ba;
     a.bb = bb;
+    a.whole_a = (ba.count() == (int64_t)A->nx * A->ny * A->nz) ? 1 : 0;
+    a.whole_b = (bb.count() == (int64_t)B->nx * B->ny * B->nz) ? 1 : 0;
     a.same_field = sf ? 1 : 0;
     timing_begin(ctx, TK_KSG, s);
     rc = launch_ksg(a, ctx->num_cus, s);

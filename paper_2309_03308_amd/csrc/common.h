@@ -146,6 +146,7 @@ struct KsgArgs {
     const float* sa;       // rows of za / zb sorted ascending, row stride ksg_p2(M), +inf padded
     const float* sb;
     int pw;                // pairs per wave chunk (<= 0: default)
+    int whole_a, whole_b;  // box covers the whole grid: local index = global index
 };
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s);
 int ksg_p2(int M);

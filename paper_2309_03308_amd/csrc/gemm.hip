@@ -10,9 +10,10 @@
 //  - workgroup = 4 waves (2 x 2), workgroup tile 128 (A rows) x 128 (B rows),
 //    wave tile 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x16_{f16,bf16}
 //    (v_mfma_f32_32x32x2_f32 for FP32 operands), FP32 accumulators;
-//  - K is consumed in chunks staged through LDS, double-buffered (global
-//    loads of chunk c+1 are in flight while chunk c is multiplied); LDS rows
-//    are padded by 16 bytes so the 16-byte operand reads are conflict-free;
+//  - K is consumed in chunks staged through LDS, double-buffered: chunk c+1
+//    is copied into the other stage right after chunk c's products are
+//    issued (other resident waves cover the load latency); LDS rows are
+//    padded by 16 bytes so the 16-byte operand reads are conflict-free;
 //  - split modes hold hi and lo parts and issue hi.hi + hi.lo + lo.hi;
 //  - persistent workgroups walk tiles in an XCD-grouped order, so the
 //    workgroups resident on one XCD (one L2) work on neighbouring tiles;
@@ -69,6 +70,52 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
+template <int PREC, int NRB>
+__device__ __forceinline__ void g_load(const char* a_hi, const char* a_lo, const char* b_hi, const char* b_lo,
+                                       int64_t row0, int64_t col0, int64_t rowb_g, int c, int tid,
+                                       uint4 (&ra)[GemmTraits<PREC>::PARTS][2],
+                                       uint4 (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
+    using T = GemmTraits<PREC>;
+    const int64_t kb = (int64_t)c * T::KC * T::ES;
+#pragma unroll
+    for (int q = 0; q < T::PARTS; ++q) {
+        const char* sa = q ? a_lo : a_hi;
+        const char* sb = q ? b_lo : b_hi;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int v = tid + G_THREADS * r;
+            ra[q][r] = *reinterpret_cast<const uint4*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+        }
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) {
+            const int v = tid + G_THREADS * r;
+            rb[q][r] = *reinterpret_cast<const uint4*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+        }
+    }
+}
+
+template <int PREC, int NRB>
+__device__ __forceinline__ void s_store(char* smem, int stage, int tid, const uint4 (&ra)[GemmTraits<PREC>::PARTS][2],
+                                        const uint4 (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
+    using T = GemmTraits<PREC>;
+    char* base = smem + stage * T::STAGE;
+#pragma unroll
+    for (int q = 0; q < T::PARTS; ++q) {
+        char* la = base + q * (G_BM + G_BN) * T::ROWB;
+        char* lb = la + G_BM * T::ROWB;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int v = tid + G_THREADS * r;
+            *reinterpret_cast<uint4*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
+        }
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) {
+            const int v = tid + G_THREADS * r;
+            *reinterpret_cast<uint4*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
+        }
+    }
+}
+
 template <int PREC>
 __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int n_ti, int n_tj) {
     using T = GemmTraits<PREC>;
@@ -101,55 +148,17 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
         // 512 x 16 B, B tile = G_BN rows x 64 B
         constexpr int NRB = G_BN * 4 / G_THREADS;
         uint4 ra[T::PARTS][2], rb[T::PARTS][NRB];
-        auto gload = [&](int c) {
-            const int64_t kb = (int64_t)c * T::KC * T::ES;
-#pragma unroll
-            for (int q = 0; q < T::PARTS; ++q) {
-                const char* sa = q ? a_lo : a_hi;
-                const char* sb = q ? b_lo : b_hi;
-#pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    int v = tid + G_THREADS * r;
-                    ra[q][r] = *reinterpret_cast<const uint4*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
-                }
-#pragma unroll
-                for (int r = 0; r < NRB; ++r) {
-                    int v = tid + G_THREADS * r;
-                    rb[q][r] = *reinterpret_cast<const uint4*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
-                }
-            }
-        };
-        auto sstore = [&](int stage) {
-            char* base = smem + stage * T::STAGE;
-#pragma unroll
-            for (int q = 0; q < T::PARTS; ++q) {
-                char* la = base + q * (G_BM + G_BN) * T::ROWB;
-                char* lb = la + G_BM * T::ROWB;
-#pragma unroll
-                for (int r = 0; r < 2; ++r) {
-                    int v = tid + G_THREADS * r;
-                    *reinterpret_cast<uint4*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
-                }
-#pragma unroll
-                for (int r = 0; r < NRB; ++r) {
-                    int v = tid + G_THREADS * r;
-                    *reinterpret_cast<uint4*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
-                }
-            }
-        };
-
         f16_t acc[G_WM][G_WN];
 #pragma unroll
         for (int i = 0; i < G_WM; ++i)
 #pragma unroll
             for (int j = 0; j < G_WN; ++j) acc[i][j] = f16_t{};
 
-        gload(0);
-        sstore(0);
+        g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, 0, tid, ra, rb);
+        s_store<PREC, NRB>(smem, 0, tid, ra, rb);
         __syncthreads();
         for (int c = 0; c < n_chunks; ++c) {
             const int stage = c & 1;
-            if (c + 1 < n_chunks) gload(c + 1);
             const char* base = smem + stage * T::STAGE;
             const char* la_hi = base + (wr * 64 + (lane & 31)) * T::ROWB;
             const char* lb_hi = base + G_BM * T::ROWB + (wc * 32 * G_WN + (lane & 31)) * T::ROWB;
@@ -192,8 +201,11 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
                         }
                 }
             }
+            // next chunk into the other stage (its readers finished before the
+            // barrier that ended the previous iteration)
             if (c + 1 < n_chunks) {
-                sstore(stage ^ 1);
+                g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, c + 1, tid, ra, rb);
+                s_store<PREC, NRB>(smem, stage ^ 1, tid, ra, rb);
             }
             __syncthreads();
         }
@@ -203,10 +215,8 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
         const bool self = g.self_col != nullptr;
         // 32x32 accumulator layout: register r of lane l holds
         // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the block.
-        auto elem_row = [&](int i, int r) -> int64_t {
-            return row0 + wr * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        };
-        auto elem_col = [&](int j) -> int64_t { return col0 + wc * 32 * G_WN + j * 32 + (lane & 31); };
+#define ELEM_ROW(i, r) (row0 + wr * 64 + (i) * 32 + 8 * ((r) >> 2) + 4 * (lane >> 5) + ((r) & 3))
+#define ELEM_COL(j) (col0 + wc * 32 * G_WN + (j) * 32 + (lane & 31))
         float m = -1.0f;
         if (!edge && !self) {
 #pragma unroll
@@ -222,7 +232,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
                 for (int j = 0; j < G_WN; ++j)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        int64_t row = elem_row(i, r), col = elem_col(j);
+                        int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
                         bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
                         if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
                     }
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         float v = acc[i][j][r];
-                        int64_t row = elem_row(i, r), col = elem_col(j);
+                        int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
                         bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
                         uint32_t lin = (uint32_t)(row * g.nb + col);
                         if (ok && fabsf(v) == wm && lin < cand) {
@@ -256,6 +266,8 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
             best_key = k > best_key ? k : best_key;
             best = wm;
         }
+#undef ELEM_ROW
+#undef ELEM_COL
     }
     if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
 }

@@ -15,9 +15,11 @@
 //  - workgroups are (B tile, slice of A blocks); a wave walks the A blocks of
 //    its workgroup's slice, so LDS traffic is B only and HBM/L2 traffic is
 //    one pass over A per B tile.
-// The epilogue is the same as the chunked kernel: per-lane max of |r|, wave
-// max by shuffles, element search only when a group reaches the wave's best,
-// one 64-bit atomicMax per wave.
+// Epilogue: each lane keeps its own running max of |r| and the group where
+// it first occurred (no cross-lane work in the sweep); at the end one wave
+// reduction finds the wave maximum, the first group holding it is recomputed
+// from the still-resident B tile, its element with the smallest linear index
+// is located, and one 64-bit atomicMax publishes (|r|, index, sign).
 #include "common.h"
 
 namespace corr {
@@ -38,6 +40,72 @@ __device__ __forceinline__ float sk_wave_max(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
     return v;
+}
+
+// A fragment of WM row blocks (all parts) straight from global memory:
+// lane (l32, half) holds row l32 of each block, 16-byte vector 2s + half.
+template <int PARTS, int WM, int KV>
+__device__ __forceinline__ void sk_load_a(const GemmArgs& g, int64_t row0, int l32, int half, int64_t rowb_g,
+                                          uint4 (&av)[PARTS][WM][KV / 2]) {
+#pragma unroll
+    for (int q = 0; q < PARTS; ++q)
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const char* src = (const char*)(q ? g.a_lo : g.a_hi) + (row0 + i * 32 + l32) * rowb_g;
+#pragma unroll
+            for (int s = 0; s < KV / 2; ++s) av[q][i][s] = *reinterpret_cast<const uint4*>(src + (2 * s + half) * 16);
+        }
+}
+
+// One group: WM x WNG blocks of 32x32, the whole K, B blocks jg.. from LDS.
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB>
+__device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int half,
+                                         const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
+    using T = SkT<PREC>;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WNG; ++j) acc[i][j] = sk_f16{};
+#pragma unroll
+    for (int s = 0; s < KV / 2; ++s) {
+#pragma unroll
+        for (int j = 0; j < WNG; ++j) {
+            const char* lb = smem + ((jg + j) * 32 + l32) * ROWB + (2 * s + half) * 16;
+            const uint4 bh = *reinterpret_cast<const uint4*>(lb);
+            uint4 bl;
+            if constexpr (T::SPLIT) bl = *reinterpret_cast<const uint4*>(lb + BN * ROWB);
+#pragma unroll
+            for (int i = 0; i < WM; ++i) {
+                if constexpr (T::F32) {
+                    const float* fa = reinterpret_cast<const float*>(&av[0][i][s]);
+                    const float* fb = reinterpret_cast<const float*>(&bh);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[e], fb[e], acc[i][j], 0, 0, 0);
+                } else if constexpr (T::BF) {
+                    const sk_b8 a8 = *reinterpret_cast<const sk_b8*>(&av[0][i][s]);
+                    const sk_b8 b8 = *reinterpret_cast<const sk_b8*>(&bh);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8, acc[i][j], 0, 0, 0);
+                    if constexpr (T::SPLIT) {
+                        const sk_b8 a8l = *reinterpret_cast<const sk_b8*>(&av[PARTS - 1][i][s]);
+                        const sk_b8 b8l = *reinterpret_cast<const sk_b8*>(&bl);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8l, acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8l, b8, acc[i][j], 0, 0, 0);
+                    }
+                } else {
+                    const sk_h8 a8 = *reinterpret_cast<const sk_h8*>(&av[0][i][s]);
+                    const sk_h8 b8 = *reinterpret_cast<const sk_h8*>(&bh);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[i][j], 0, 0, 0);
+                    if constexpr (T::SPLIT) {
+                        const sk_h8 a8l = *reinterpret_cast<const sk_h8*>(&av[PARTS - 1][i][s]);
+                        const sk_h8 b8l = *reinterpret_cast<const sk_h8*>(&bl);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8l, acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8l, b8, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
 }
 
 // KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
@@ -78,78 +146,27 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
     const int64_t ab_begin = (int64_t)slice * n_ablk_per_wg;
     int64_t ab_end = ab_begin + n_ablk_per_wg;
     if (ab_end > n_ablk) ab_end = n_ablk;
-
-    float best = -1.0f;
-    unsigned long long best_key = 0;
     const bool self = g.self_col != nullptr;
     const int32_t nb = (int32_t)g.nb;
 
+    // Per-lane running maximum and the (A block, column group) where it
+    // first occurred; no cross-lane work inside the sweep.
+    float lane_best = -1.0f;
+    int lane_ab = -1, lane_jg = -1;
+
+    uint4 av[PARTS][WM][KV / 2];
+    sk_f16 acc[WM][WNG];
     for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
         const int64_t row0 = ab * 32 * WM;
-        // A fragment in registers: av[part][i][vector]
-        uint4 av[PARTS][WM][KV / 2];
-#pragma unroll
-        for (int q = 0; q < PARTS; ++q)
-#pragma unroll
-            for (int i = 0; i < WM; ++i) {
-                const char* src = (const char*)(q ? g.a_lo : g.a_hi) + (row0 + i * 32 + l32) * rowb_g;
-#pragma unroll
-                for (int s = 0; s < KV / 2; ++s)
-                    av[q][i][s] = *reinterpret_cast<const uint4*>(src + (2 * s + half) * 16);
-            }
+        sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
         const bool edge_rows = row0 + 32 * WM > g.na;
-
+#pragma unroll 1
         for (int jg = 0; jg < BN / 32; jg += WNG) {
-            sk_f16 acc[WM][WNG];
-#pragma unroll
-            for (int i = 0; i < WM; ++i)
-#pragma unroll
-                for (int j = 0; j < WNG; ++j) acc[i][j] = sk_f16{};
-#pragma unroll
-            for (int s = 0; s < KV / 2; ++s) {
-#pragma unroll
-                for (int j = 0; j < WNG; ++j) {
-                    const char* lb = smem + ((jg + j) * 32 + l32) * ROWB + (2 * s + half) * 16;
-                    uint4 bh = *reinterpret_cast<const uint4*>(lb);
-                    uint4 bl;
-                    if constexpr (T::SPLIT) bl = *reinterpret_cast<const uint4*>(lb + BN * ROWB);
-#pragma unroll
-                    for (int i = 0; i < WM; ++i) {
-                        if constexpr (T::F32) {
-                            const float* fa = reinterpret_cast<const float*>(&av[0][i][s]);
-                            const float* fb = reinterpret_cast<const float*>(&bh);
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[e], fb[e], acc[i][j], 0, 0, 0);
-                        } else if constexpr (T::BF) {
-                            sk_b8 a8 = *reinterpret_cast<const sk_b8*>(&av[0][i][s]);
-                            sk_b8 b8 = *reinterpret_cast<const sk_b8*>(&bh);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8, acc[i][j], 0, 0, 0);
-                            if constexpr (T::SPLIT) {
-                                sk_b8 a8l = *reinterpret_cast<const sk_b8*>(&av[PARTS - 1][i][s]);
-                                sk_b8 b8l = *reinterpret_cast<const sk_b8*>(&bl);
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8l, acc[i][j], 0, 0, 0);
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8l, b8, acc[i][j], 0, 0, 0);
-                            }
-                        } else {
-                            sk_h8 a8 = *reinterpret_cast<const sk_h8*>(&av[0][i][s]);
-                            sk_h8 b8 = *reinterpret_cast<const sk_h8*>(&bh);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[i][j], 0, 0, 0);
-                            if constexpr (T::SPLIT) {
-                                sk_h8 a8l = *reinterpret_cast<const sk_h8*>(&av[PARTS - 1][i][s]);
-                                sk_h8 b8l = *reinterpret_cast<const sk_h8*>(&bl);
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8l, acc[i][j], 0, 0, 0);
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8l, b8, acc[i][j], 0, 0, 0);
-                            }
-                        }
-                    }
-                }
-            }
-            // ---- epilogue for this 32*WM x 32*WNG group
+            sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
             const int32_t c0 = (int32_t)(col0 + jg * 32);
-            const bool edge = edge_rows || (c0 + 32 * WNG > nb);
+            const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
             float m = -1.0f;
-            if (!edge && !self) {
+            if (!edge) {
 #pragma unroll
                 for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -164,45 +181,61 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
                     for (int j = 0; j < WNG; ++j)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                            int32_t col = c0 + j * 32 + l32;
-                            bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
+                            const int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            const int32_t col = c0 + j * 32 + l32;
+                            const bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
                             if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
                         }
             }
-            const float wm = sk_wave_max(m);
-            if (wm >= 0.0f && wm >= best) {
-                uint32_t cand = 0xffffffffu, neg = 0;
-#pragma unroll
-                for (int i = 0; i < WM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WNG; ++j)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            // 32x32 accumulator layout: register r of lane l holds
-                            // row 8*(r/4) + 4*(l/32) + r%4, column l%32
-                            int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                            int32_t col = c0 + j * 32 + l32;
-                            float v = acc[i][j][r];
-                            bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
-                            uint32_t lin = (uint32_t)row * (uint32_t)nb + (uint32_t)col;
-                            if (ok && fabsf(v) == wm && lin < cand) {
-                                cand = lin;
-                                neg = v < 0.0f ? 1u : 0u;
-                            }
-                        }
-                unsigned long long k = (cand == 0xffffffffu) ? 0ull : make_key(wm, cand, neg);
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    unsigned long long o = __shfl_xor(k, off, 64);
-                    k = o > k ? o : k;
-                }
-                best_key = k > best_key ? k : best_key;
-                best = wm;
+            if (m > lane_best) {
+                lane_best = m;
+                lane_ab = (int)ab;
+                lane_jg = jg;
             }
         }
     }
-    if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
+
+    // ---- one wave reduction; the first group (in sweep order) holding the
+    // wave maximum is recomputed to find its element
+    const float wb = sk_wave_max(lane_best);
+    if (wb < 0.0f) return;
+    int code = (lane_best == wb) ? lane_ab * (BN / 32) + lane_jg : 0x7fffffff;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(code, off, 64);
+        code = o < code ? o : code;
+    }
+    const int ab = code / (BN / 32), jg = code - ab * (BN / 32);
+    const int64_t row0 = (int64_t)ab * 32 * WM;
+    sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
+    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
+    const int32_t c0 = (int32_t)(col0 + jg * 32);
+    uint32_t cand = 0xffffffffu, neg = 0;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WNG; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                // 32x32 accumulator layout: register r of lane l holds
+                // row 8*(r/4) + 4*(l/32) + r%4, column l%32
+                const int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                const int32_t col = c0 + j * 32 + l32;
+                const float v = acc[i][j][r];
+                const bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
+                const uint32_t lin = (uint32_t)row * (uint32_t)nb + (uint32_t)col;
+                if (ok && fabsf(v) == wb && lin < cand) {
+                    cand = lin;
+                    neg = v < 0.0f ? 1u : 0u;
+                }
+            }
+    unsigned long long key = (cand == 0xffffffffu) ? 0ull : make_key(wb, cand, neg);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off, 64);
+        key = o > key ? o : key;
+    }
+    if (lane == 0 && key) atomicMax(g.key, key);
 }
 
 // ---------------------------------------------------------------- dispatch

@@ -42,41 +42,47 @@ __device__ __forceinline__ void topk_insert(float (&t)[KP1], float d) {
     t[0] = fminf(t[0], d);
 }
 
-// number of leading entries s of the sorted row with fl32(x - s) >= eps
-// (first index of the run |x - s| < eps); p2 is a power of two > M, row
-// padded with +inf
-__device__ __forceinline__ int lower_run(const float* s, int p2, float x, float eps) {
-    int pos = 0;
+// Marginal counts by binary search on the sorted marginals (p2 a power of
+// two > M, rows padded with +inf). For each marginal two runs are located at
+// once: lo = number of leading s with fl32(x - s) >= eps, hi = number of
+// leading s with fl32(x - s) > -eps; the j with |fl32(x - x_j)| < eps are
+// exactly the hi - lo entries in between. The four searches are interleaved
+// so their LDS reads overlap.
+__device__ __forceinline__ void run_counts(const float* sx, const float* sy, int p2, float x, float y, float eps,
+                                           int& cx, int& cy) {
+    int lx = 0, ux = 0, ly = 0, uy = 0;
     for (int step = p2 >> 1; step >= 1; step >>= 1) {
-        float v = s[pos + step - 1];
-        pos += (x - v < eps) ? 0 : step;
+        const float a0 = sx[lx + step - 1], a1 = sx[ux + step - 1];
+        const float b0 = sy[ly + step - 1], b1 = sy[uy + step - 1];
+        lx += (x - a0 < eps) ? 0 : step;
+        ux += (x - a1 > -eps) ? step : 0;
+        ly += (y - b0 < eps) ? 0 : step;
+        uy += (y - b1 > -eps) ? step : 0;
     }
-    return pos;
-}
-// number of leading entries with fl32(x - s) > -eps (end of the run)
-__device__ __forceinline__ int upper_run(const float* s, int p2, float x, float eps) {
-    int pos = 0;
-    for (int step = p2 >> 1; step >= 1; step >>= 1) {
-        float v = s[pos + step - 1];
-        pos += (x - v > -eps) ? step : 0;
-    }
-    return pos;
+    cx = ux - lx;
+    cy = uy - ly;
 }
 
 struct KsgLayout {
     int mpad2;      // M rounded up to even (interleaved samples, float2 entries)
-    int p2;         // power of two >= M (sorted marginals)
-    int pw;         // pairs per wave chunk
+    int p2;         // power of two > M (sorted marginals)
+    int pw;         // pairs per wave chunk (divides 64)
     int slot_f;     // floats per pair slot
-    int wave_f;     // floats per wave (slots + item terms as doubles)
+    int wave_f;     // floats per wave (slots, packed counts, pair info)
+    int psi_f;      // floats of the block-shared digamma table
 };
 
 template <int KP1>
 __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L) {
     extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float* wbase = lds_f + wave * L.wave_f;
+    // block-shared: digamma table psi[0..M] (FP64), then per wave: pair slots,
+    // packed counts, per-pair (la, lb, flags)
+    double* psi = reinterpret_cast<double*>(lds_f);
+    float* wbase = lds_f + L.psi_f + wave * L.wave_f;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(wbase + L.pw * L.slot_f);  // packed n_x | n_y << 16
+    int* pinfo = reinterpret_cast<int*>(cnt + L.pw * a.M);                 // [pw][4]: la, lb, state, in_max
+    for (int v = threadIdx.x; v <= a.M; v += 256) psi[v] = a.psi[v];
     const int M = a.M;
     const int k = a.k;
     const int64_t nb = a.bb.count();
@@ -87,37 +93,55 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
 
     for (int64_t base = (int64_t)blockIdx.x * chunk_pairs; base < n_total; base += (int64_t)gridDim.x * chunk_pairs) {
         const int64_t wbase_pair = base + (int64_t)wave * L.pw;
+        // ---- per-pair index math, one lane per pair
+        // state: 0 = nothing to evaluate, 1 = evaluate, 2 = constant point (MI 0)
+        if (lane < L.pw) {
+            const int64_t t = wbase_pair + lane;
+            int la = -1, lb = -1, state = 0, in_max = 0;
+            if (t < n_total) {
+                bool same = false;
+                if (a.pairs) {
+                    const int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
+                    la = a.whole_a ? ga : (int)a.ba.local(ga);
+                    lb = a.whole_b ? gb : (int)a.bb.local(gb);
+                    same = ga == gb;
+                } else {
+                    const int32_t tt = (int32_t)t, nb32 = (int32_t)nb;
+                    la = tt / nb32;
+                    lb = tt - la * nb32;
+                    same = a.ba.global(la) == a.bb.global(lb);
+                }
+                if (la >= 0 && lb >= 0) {
+                    state = 1;
+                    if (a.inv_a && (a.inv_a[la] == 0.0f || a.inv_b[lb] == 0.0f)) state = 2;
+                    in_max = (a.key != nullptr) && !(a.same_field && same);
+                }
+            }
+            int* pi = pinfo + 4 * lane;
+            pi[0] = la;
+            pi[1] = lb;
+            pi[2] = state;
+            pi[3] = in_max;
+        }
+        __syncthreads();
         // ---- stage the wave's pairs (all waves reach every barrier)
         for (int q = 0; q < L.pw; ++q) {
-            const int64_t t = wbase_pair + q;
+            const int* pi = pinfo + 4 * q;
+            if (pi[2] != 1) continue;
             float* slot = wbase + q * L.slot_f;
             float2* xy = reinterpret_cast<float2*>(slot);
             float* sx = slot + 2 * L.mpad2;
             float* sy = sx + L.p2;
-            int64_t la = -1, lb = -1;
-            bool ok = false;
-            if (t < n_total) {
-                if (a.pairs) {
-                    la = a.ba.local(a.pairs[2 * t]);
-                    lb = a.bb.local(a.pairs[2 * t + 1]);
-                } else {
-                    la = t / nb;
-                    lb = t - la * nb;
-                }
-                ok = la >= 0 && lb >= 0;
-                if (ok && a.inv_a) ok = (a.inv_a[la] != 0.0f) && (a.inv_b[lb] != 0.0f);
-            }
-            if (ok) {
-                const float* xa = a.za + la * a.ld;
-                const float* yb = a.zb + lb * a.ld;
-                const float* sxa = a.sa + la * L.p2;
-                const float* syb = a.sb + lb * L.p2;
-                for (int j = lane; j < L.mpad2; j += 64)
-                    xy[j] = (j < M) ? make_float2(xa[j], yb[j]) : make_float2(inf, inf);
-                for (int j = lane; j < L.p2; j += 64) {
-                    sx[j] = sxa[j];
-                    sy[j] = syb[j];
-                }
+            const int64_t la = pi[0], lb = pi[1];
+            const float* xa = a.za + la * a.ld;
+            const float* yb = a.zb + lb * a.ld;
+            const float* sxa = a.sa + la * L.p2;
+            const float* syb = a.sb + lb * L.p2;
+            for (int j = lane; j < L.mpad2; j += 64)
+                xy[j] = (j < M) ? make_float2(xa[j], yb[j]) : make_float2(inf, inf);
+            for (int j = lane; j < L.p2; j += 64) {
+                sx[j] = sxa[j];
+                sy[j] = syb[j];
             }
         }
         __syncthreads();
@@ -146,57 +170,51 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             const float* sx = slot + 2 * L.mpad2;
             const float* sy = sx + L.p2;
             const int self = eps > 0.0f ? 1 : 0;
-            int nx = upper_run(sx, L.p2, me.x, eps) - lower_run(sx, L.p2, me.x, eps) - self;
-            int ny = upper_run(sy, L.p2, me.y, eps) - lower_run(sy, L.p2, me.y, eps) - self;
+            int nx, ny;
+            run_counts(sx, sy, L.p2, me.x, me.y, eps, nx, ny);
+            nx -= self;
+            ny -= self;
             nx = nx < 0 ? 0 : nx;
             ny = ny < 0 ? 0 : ny;
             if (u < n_items) {
                 cnt[u] = (uint32_t)nx | ((uint32_t)ny << 16);
                 const int64_t t = wbase_pair + q;
-                if (a.counts_out && t < n_total)
+                if (a.counts_out && pinfo[4 * q + 2] == 1)
                     reinterpret_cast<int2*>(a.counts_out)[t * M + i] = make_int2(nx, ny);
             }
         }
         __syncthreads();
-        // ---- per pair: one lane sums the M terms in sample order
-        if (lane < L.pw) {
-            const int q = lane;
+        // ---- per pair: G = 64 / pw lanes sum the digamma terms; lane r of a
+        // group takes samples r, r + G, ... in order, then a fixed xor tree
+        // combines the group -- the same order on every run
+        {
+            const int G = 64 / L.pw;
+            const int q = lane / G, r = lane - q * G;
+            const int* pi = pinfo + 4 * q;
+            double acc = 0.0;
+            if (pi[2] == 1) {
+                const uint32_t* cq = cnt + q * M;
+                for (int i = r; i < M; i += G) {
+                    const uint32_t c = cq[i];
+                    acc += psi[(c & 0xffffu) + 1] + psi[(c >> 16) + 1];
+                }
+            }
+            for (int off = G >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
             const int64_t t = wbase_pair + q;
-            if (t < n_total) {
-                int64_t la, lb;
-                bool in_max = a.key != nullptr;
-                if (a.pairs) {
-                    int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
-                    la = a.ba.local(ga);
-                    lb = a.bb.local(gb);
-                    if (a.same_field && ga == gb) in_max = false;
-                } else {
-                    la = t / nb;
-                    lb = t - la * nb;
-                    if (a.same_field && a.ba.global(la) == a.bb.global(lb)) in_max = false;
-                }
-                bool ok = la >= 0 && lb >= 0;
-                if (!ok) in_max = false;
-                bool zero = ok && a.inv_a && ((a.inv_a[la] == 0.0f) || (a.inv_b[lb] == 0.0f));
+            if (r == 0 && t < n_total) {
+                const int state = pi[2];
                 float mi = 0.0f;
-                if (ok && !zero) {
-                    double acc = 0.0;
-                    const uint32_t* cq = cnt + q * M;
-                    for (int i = 0; i < M; ++i) {
-                        uint32_t c = cq[i];
-                        acc += a.psi[(c & 0xffffu) + 1] + a.psi[(c >> 16) + 1];
-                    }
-                    mi = (float)(a.psi[M] + a.psi[k] - acc / (double)M);
-                } else if (a.counts_out) {
-                    int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M;
-                    for (int i = 0; i < M; ++i) c[i] = make_int2(0, 0);
-                }
+                if (state == 1) mi = (float)(psi[M] + psi[k] - acc / (double)M);
                 if (a.mi_out) a.mi_out[t] = mi;
-                if (in_max) {
-                    unsigned long long key = make_key(mi, (uint32_t)(la * nb + lb), 0u);
+                if (pi[3] && state != 0) {
+                    const unsigned long long key = make_key(mi, (uint32_t)((int64_t)pi[0] * nb + pi[1]), 0u);
                     best = key > best ? key : best;
                     ++n_in_max;
                 }
+            }
+            if (a.counts_out && t < n_total && pi[2] != 1) {
+                int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M;
+                for (int i = r; i < M; i += G) c[i] = make_int2(0, 0);
             }
         }
         __syncthreads();  // slots and terms are rewritten by the next chunk
@@ -279,12 +297,16 @@ static KsgLayout ksg_layout(int M, int pw) {
     L.pw = pw > 0 ? pw : ksg_default_pw(M);
     L.slot_f = 2 * L.mpad2 + 2 * L.p2;
     L.slot_f = (L.slot_f + 3) & ~3;
-    L.wave_f = L.pw * L.slot_f + L.pw * M;  // + packed counts per item
+    L.wave_f = L.pw * L.slot_f + L.pw * M + 4 * L.pw;  // + packed counts, pair info
     L.wave_f = (L.wave_f + 3) & ~3;
+    L.psi_f = (2 * (M + 1) + 3) & ~3;
     return L;
 }
 
-size_t ksg_lds_bytes(int M, int pw) { return (size_t)KSG_WAVES * ksg_layout(M, pw).wave_f * sizeof(float); }
+size_t ksg_lds_bytes(int M, int pw) {
+    const KsgLayout L = ksg_layout(M, pw);
+    return ((size_t)KSG_WAVES * L.wave_f + L.psi_f) * sizeof(float);
+}
 
 template <int KP1>
 static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, dim3 grid, size_t lds, hipStream_t s) {
@@ -303,7 +325,8 @@ int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     int64_t n_total = a.pairs ? a.n : a.ba.count() * a.bb.count();
     if (n_total == 0) return CORR_OK;
     const KsgLayout L = ksg_layout(a.M, a.pw);
-    const size_t lds = (size_t)KSG_WAVES * L.wave_f * sizeof(float);
+    if (64 % L.pw) return fail(CORR_EINVAL, "KSG: pairs per wave must divide 64");
+    const size_t lds = ksg_lds_bytes(a.M, a.pw);
     if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
     const int64_t chunk_pairs = (int64_t)KSG_WAVES * L.pw;
     int64_t blocks = (n_total + chunk_pairs - 1) / chunk_pairs;
