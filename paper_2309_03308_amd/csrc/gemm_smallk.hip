@@ -12,9 +12,10 @@
 //    WM x WNG x K/16 MFMA (32x32x16 f16/bf16, or 32x32x2 f32 with a K
 //    permutation that lets one float4 read feed four steps) into FP32
 //    accumulators, then folds |r| of the group into its running maximum;
-//  - workgroups are (B tile, slice of A blocks); a wave walks the A blocks of
-//    its workgroup's slice, so LDS traffic is B only and HBM/L2 traffic is
-//    one pass over A per B tile.
+//  - workgroups are (B tile, slice of 4 x apw A blocks); a wave walks every
+//    fourth A block of the slice (optionally prefetching the next fragment
+//    into a second register buffer), so LDS traffic is B only and L2 traffic
+//    is one pass over A per B tile; many small slices keep the tail short.
 // Epilogue: each lane keeps its own running max of |r| and the group where
 // it first occurred (no cross-lane work in the sweep); at the end one wave
 // reduction finds the wave maximum, the first group holding it is recomputed
@@ -108,8 +109,50 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
     }
 }
 
+// All column groups of the B tile against one A block, folding |r| into the
+// lane's running maximum (strict >: the first occurrence in sweep order).
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB>
+__device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, int64_t ab, int64_t col0, int l32,
+                                         int half, bool self, int32_t nb, const uint4 (&av)[PARTS][WM][KV / 2],
+                                         sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
+    const int64_t row0 = ab * 32 * WM;
+    const bool edge_rows = row0 + 32 * WM > g.na;
+#pragma unroll 1
+    for (int jg = 0; jg < BN / 32; jg += WNG) {
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
+        const int32_t c0 = (int32_t)(col0 + jg * 32);
+        const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
+        float m = -1.0f;
+        if (!edge) {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; r += 2) m = fmaxf(m, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
+        } else {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                        const int32_t col = c0 + j * 32 + l32;
+                        const bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
+                        if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
+                    }
+        }
+        if (m > lane_best) {
+            lane_best = m;
+            lane_ab = (int)ab;
+            lane_jg = jg;
+        }
+    }
+}
+
 // KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
-template <int PREC, int KV, int WM, int WNG, int BN>
+template <int PREC, int KV, int WM, int WNG, int BN, int PF>
 __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_ablk_per_wg, int n_tj) {
     using T = SkT<PREC>;
     constexpr int PARTS = T::SPLIT ? 2 : 1;
@@ -156,42 +199,28 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
 
     uint4 av[PARTS][WM][KV / 2];
     sk_f16 acc[WM][WNG];
-    for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
-        const int64_t row0 = ab * 32 * WM;
-        sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
-        const bool edge_rows = row0 + 32 * WM > g.na;
-#pragma unroll 1
-        for (int jg = 0; jg < BN / 32; jg += WNG) {
-            sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
-            const int32_t c0 = (int32_t)(col0 + jg * 32);
-            const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
-            float m = -1.0f;
-            if (!edge) {
-#pragma unroll
-                for (int i = 0; i < WM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WNG; ++j)
-#pragma unroll
-                        for (int r = 0; r < 16; r += 2)
-                            m = fmaxf(m, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
-            } else {
-#pragma unroll
-                for (int i = 0; i < WM; ++i)
-#pragma unroll
-                    for (int j = 0; j < WNG; ++j)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int32_t row = (int32_t)row0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                            const int32_t col = c0 + j * 32 + l32;
-                            const bool ok = row < g.na && col < nb && !(self && g.self_col[row] == col);
-                            if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
-                        }
-            }
-            if (m > lane_best) {
-                lane_best = m;
-                lane_ab = (int)ab;
-                lane_jg = jg;
-            }
+    if constexpr (!PF) {
+        for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
+            sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
+                                                          lane_ab, lane_jg);
+        }
+    } else {
+        // A fragments double-buffered in registers: the next block's loads
+        // are in flight while the current block is multiplied
+        uint4 av2[PARTS][WM][KV / 2];
+        int64_t ab = ab_begin + wave;
+        if (ab < ab_end) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
+        while (ab < ab_end) {
+            if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
+                                                          lane_ab, lane_jg);
+            ab += 4;
+            if (ab >= ab_end) break;
+            if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av2, acc, lane_best,
+                                                          lane_ab, lane_jg);
+            ab += 4;
         }
     }
 
@@ -240,32 +269,47 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
 
 // ---------------------------------------------------------------- dispatch
 struct SkCfg {
-    int wm, wng, bn;
+    int wm, wng, bn, pf, apw;  // row blocks/wave, column blocks/group, B tile rows, A prefetch, A blocks per wave
 };
 
-template <int PREC, int KV, int WM, int WNG, int BN>
-static int launch_sk_t(const GemmArgs& g, int num_cus, int wg_per_cu, hipStream_t s) {
+// Tile configurations the autotuner chooses from (index = config id).
+// apw = 0: long-lived workgroups, about two per CU (each loads its B tile
+// once and sweeps a long slice of A blocks).
+static const SkCfg kSkCfgs[] = {
+    {2, 2, 256, 0, 0}, {1, 4, 256, 0, 0}, {2, 2, 128, 0, 0}, {1, 2, 128, 0, 0},
+    {1, 2, 128, 1, 0}, {1, 4, 256, 1, 0}, {2, 2, 128, 1, 0}, {2, 2, 128, 0, 8},
+};
+constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
+
+template <int PREC, int KV, int WM, int WNG, int BN, int PF>
+static int launch_sk_t(const GemmArgs& g, int apw, int num_cus, hipStream_t s) {
     constexpr int PARTS = SkT<PREC>::SPLIT ? 2 : 1;
     constexpr int ROWB = KV * 16 + 16;
     const size_t lds = (size_t)PARTS * BN * ROWB;
     const int n_tj = (int)(g.nb_pad / BN);
     const int64_t n_ablk = g.na_pad / (32 * WM);
-    // slices per B tile so that the grid holds about wg_per_cu workgroups per CU
-    int64_t want = (int64_t)num_cus * wg_per_cu;
-    int64_t slices = (want + n_tj - 1) / n_tj;
-    if (slices < 1) slices = 1;
-    if (slices > n_ablk) slices = n_ablk;
-    int64_t per = (n_ablk + slices - 1) / slices;
-    per = (per + 3) / 4 * 4;  // whole rounds of the 4 waves
-    slices = (n_ablk + per - 1) / per;
+    // each workgroup: one B tile and a slice of A blocks (4 * apw of them, or
+    // with apw = 0 enough slices for about two workgroups per CU)
+    int64_t per;
+    if (apw > 0) {
+        per = 4 * (int64_t)apw;
+    } else {
+        int64_t want = (int64_t)num_cus * 2;
+        int64_t sl = (want + n_tj - 1) / n_tj;
+        if (sl < 1) sl = 1;
+        if (sl > n_ablk) sl = n_ablk;
+        per = (n_ablk + sl - 1) / sl;
+        per = (per + 3) / 4 * 4;
+    }
+    const int64_t slices = (n_ablk + per - 1) / per;
     const int64_t grid = slices * n_tj;
     static bool attr = false;
     if (!attr) {
-        CORR_HIP(hipFuncSetAttribute((const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN>,
+        CORR_HIP(hipFuncSetAttribute((const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    gemm_smallk_kernel<PREC, KV, WM, WNG, BN><<<dim3((unsigned)grid), 256, lds, s>>>(g, (int)per, n_tj);
+    gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF><<<dim3((unsigned)grid), 256, lds, s>>>(g, (int)per, n_tj);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -273,30 +317,30 @@ static int launch_sk_t(const GemmArgs& g, int num_cus, int wg_per_cu, hipStream_
 // Small-K contraction K values: members are zero-padded to 64, 112 or 128.
 int smallk_pad_K(int M) { return M <= 64 ? 64 : (M <= 112 ? 112 : 128); }
 
-template <int PREC, int WM, int WNG, int BN>
-static int launch_sk_k(const GemmArgs& g, int num_cus, int wg_per_cu, hipStream_t s) {
+template <int PREC, int WM, int WNG, int BN, int PF>
+static int launch_sk_k(const GemmArgs& g, int apw, int num_cus, hipStream_t s) {
     constexpr int ES = SkT<PREC>::ES;
     switch (g.K) {
-        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
-        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
-        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN>(g, num_cus, wg_per_cu, s);
+        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
+        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
+        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
     }
     return fail(CORR_EUNSUPPORTED, "small-K contraction: K must be 64, 112 or 128");
 }
 
-// Tile configurations the autotuner chooses from (index = config id):
-// {row blocks of 32 per wave, column blocks of 32 per group, B tile rows}.
-static const SkCfg kSkCfgs[] = {{2, 2, 256}, {1, 4, 256}, {2, 2, 128}, {1, 2, 128}};
-constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
-
 template <int PREC>
-static int launch_sk_p(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {
+static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s) {
     constexpr bool SPLIT = SkT<PREC>::SPLIT;
+    const int apw = kSkCfgs[cfg].apw;
     switch (cfg) {
-        case 0: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 256>(g, num_cus, 2, s); break;
-        case 1: return launch_sk_k<PREC, 1, 4, 256>(g, num_cus, 2, s);
-        case 2: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 128>(g, num_cus, 2, s); break;
-        case 3: return launch_sk_k<PREC, 1, 2, 128>(g, num_cus, 2, s);
+        case 0: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 256, 0>(g, apw, nc, s); break;
+        case 1: return launch_sk_k<PREC, 1, 4, 256, 0>(g, apw, nc, s);
+        case 2:
+        case 7: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 128, 0>(g, apw, nc, s); break;
+        case 3: return launch_sk_k<PREC, 1, 2, 128, 0>(g, apw, nc, s);
+        case 4: return launch_sk_k<PREC, 1, 2, 128, 1>(g, apw, nc, s);
+        case 5: return launch_sk_k<PREC, 1, 4, 256, 1>(g, apw, nc, s);
+        case 6: if constexpr (!SPLIT && PREC != CORR_PREC_F32) return launch_sk_k<PREC, 2, 2, 128, 1>(g, apw, nc, s); break;
     }
     return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
 }
@@ -304,9 +348,14 @@ static int launch_sk_p(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {
 int smallk_num_configs() { return kNumSkCfgs; }
 int smallk_row_pad(int cfg) { return 32 * kSkCfgs[cfg].wm; }
 int smallk_col_pad(int cfg) { return kSkCfgs[cfg].bn; }
-// split modes keep hi and lo A fragments; only one-row-block configs fit
+// Register budget: split modes keep hi and lo A fragments (one row block
+// only); FP32 operands with two row blocks cannot also double-buffer A.
 bool smallk_config_ok(int prec, int cfg) {
-    return cfg >= 0 && cfg < kNumSkCfgs && (!prec_split(prec) || kSkCfgs[cfg].wm == 1);
+    if (cfg < 0 || cfg >= kNumSkCfgs) return false;
+    const SkCfg& c = kSkCfgs[cfg];
+    if (prec_split(prec) && c.wm != 1) return false;
+    if (prec == CORR_PREC_F32 && c.wm == 2 && c.pf) return false;  // cfg 6
+    return true;
 }
 
 int launch_gemm_smallk(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {

@@ -1,0 +1,116 @@
+"""Pins for the BOS oracle (Sec. 3.1): library routines and closed forms,
+not the oracle's formulas retyped."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bos_ref as B
+
+
+def test_philox_matches_numpy():
+    # numpy's Philox bit generator is Philox4x64-10; its first block uses
+    # counter + 1 (it increments before generating)
+    for key, ctr in [((7, 0x636F7272), (0, 0, 0, 0)), ((123456789, 42), (5, 1, 99, 3)),
+                     ((2**63 + 11, 2**64 - 1), (2**64 - 2, 2**64 - 1, 17, 2**40))]:
+        bg = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(ctr, np.uint64))
+        got = [int(v) for v in bg.random_raw(4)]
+        c = list(ctr)
+        c[0] = (c[0] + 1) & B.MASK64
+        if c[0] == 0:
+            c[1] = (c[1] + 1) & B.MASK64
+        assert B.philox4x64(c, key) == got
+
+
+def test_matern_matches_sklearn():
+    from sklearn.gaussian_process.kernels import Matern
+    rng = np.random.default_rng(0)
+    X1, X2 = rng.uniform(0, 20, (7, 6)), rng.uniform(0, 20, (5, 6))
+    ref = Matern(length_scale=3.0, nu=2.5)(X1, X2)
+    assert np.allclose(B.matern52(X1, X2, 3.0), ref, rtol=1e-12, atol=1e-14)
+
+
+def test_gp_posterior_matches_sklearn():
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import Matern
+    rng = np.random.default_rng(1)
+    X = rng.integers(0, 16, (40, 6)).astype(float)
+    X = np.unique(X, axis=0)
+    y = np.sin(X.sum(1) / 7.0) + 0.1 * rng.standard_normal(X.shape[0])
+    yt = B.standardize_y(y)
+    Xc = rng.uniform(0, 15, (200, 6))
+    mu, var = B.gp_posterior(X, yt, Xc, 3.0, 1e-6)
+    gp = GaussianProcessRegressor(kernel=Matern(length_scale=3.0, nu=2.5), alpha=1e-6, optimizer=None,
+                                  normalize_y=False).fit(X, yt)
+    m2, s2 = gp.predict(Xc, return_std=True)
+    assert np.allclose(mu, m2, rtol=0, atol=1e-8)
+    assert np.allclose(np.sqrt(var), s2, rtol=0, atol=1e-6)
+
+
+def test_believer_keeps_means_and_matches_refit():
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import Matern
+    rng = np.random.default_rng(2)
+    X = np.unique(rng.integers(0, 12, (25, 6)).astype(float), axis=0)
+    yt = B.standardize_y(rng.standard_normal(X.shape[0]))
+    th = rng.uniform(0, 11, (64, 6))
+    cfg = B.BosConfig()
+    picks, mu0 = B.believer_picks(cfg, X, yt, th, 3)
+    assert len(set(picks)) == 3
+    # refit with the believer values: means at all candidates unchanged
+    Xe = np.vstack([X, th[picks]])
+    ye = np.concatenate([yt, mu0[picks]])
+    gp = GaussianProcessRegressor(kernel=Matern(length_scale=3.0, nu=2.5), alpha=1e-6, optimizer=None).fit(Xe, ye)
+    assert np.allclose(gp.predict(th), mu0, atol=1e-6)
+    # the first pick is the plain UCB argmax
+    mu, var = B.gp_posterior(X, yt, th, 3.0, 1e-6)
+    assert picks[0] == int(np.argmax(mu + 0.5 * np.sqrt(var)))
+
+
+def test_schedule_is_a_composition_of_80():
+    for pair in range(200):
+        s = B.schedule(B.BosConfig(seed=5), pair)
+        assert sum(s) == 80 and all(8 <= b <= 64 and b % 8 == 0 for b in s)
+    lens = {len(B.schedule(B.BosConfig(seed=5), p)) for p in range(200)}
+    assert len(lens) > 3  # uneven across pairs
+
+
+def test_rounding_is_bernoulli_of_the_fraction():
+    cfg = B.BosConfig(seed=9)
+    dims = (32, 32, 20, 32, 32, 20)
+    th = np.array([3.0, 7.25, 0.5, 30.9, 12.0, 18.75])
+    ups = np.zeros(6)
+    n = 4000
+    for s in range(n):
+        c = B.round_cell(cfg, 0, s, th, dims)
+        ups += (c > np.floor(th))
+    frac = th - np.floor(th)
+    assert np.all(np.abs(ups / n - frac) < 4 * np.sqrt(frac * (1 - frac) / n) + 1e-12)
+    assert (B.round_cell(cfg, 0, 0, np.array([31.0, 31, 19, 0, 0, 0]), dims) == [31, 31, 19, 0, 0, 0]).all()
+
+
+def test_bos_finds_analytic_maximum_of_6d_normal():
+    # a 6-variate normal PDF in place of a correlation (its grid maximum is
+    # found by brute force): mean normalised error of BOS at 100 samples,
+    # against 100 uniform random samples of the same objective
+    rng = np.random.default_rng(4)
+    dims = (8, 8, 8, 8, 8, 8)
+    grid = np.stack(np.meshgrid(*[np.arange(8)] * 6, indexing="ij"), -1).reshape(-1, 6).astype(float)
+    errs, rnd = [], []
+    for t in range(6):
+        mean = rng.uniform(1, 6, 6)
+        A = rng.standard_normal((6, 6))
+        cov = A @ A.T / 6 + 6.0 * np.eye(6)
+        P = np.linalg.inv(cov)
+
+        def f(c):
+            d = np.asarray(c, float) - mean
+            return np.exp(-0.5 * np.einsum("ni,ij,nj->n", d, P, d))
+
+        true_max = f(grid).max()
+        res = B.run_pair(B.BosConfig(seed=100 + t), t, dims, f)
+        assert res["n_evaluated"] <= 100
+        errs.append((true_max - res["value"]) / true_max)
+        rnd.append((true_max - f(rng.integers(0, 8, (100, 6))).max()) / true_max)
+    assert np.mean(errs) <= 0.05, errs
+    assert np.mean(errs) <= np.mean(rnd) / 4, (errs, rnd)
