@@ -1,0 +1,81 @@
+/*
+ * mlp.h -- learned proposal for batched BOS (part of libcorr).
+ *
+ * A small multilayer perceptron maps a region pair's summary to the maxima
+ * BOS searches for (Sec. 3.1) and a proposed location; its prediction seeds
+ * the sampler through bos_set_prior. The paper names a network trained to
+ * predict correlation values as future work (Sec. 7); here it is trained on
+ * records the method itself produces (exhaustive / BOS maxima).
+ *
+ * Network: x (n_in) -> silu(x W1 + b1) -> silu(. W2 + b2) -> . W3 + b3 (n_out),
+ * silu(z) = z / (1 + e^-z), weights W [in][out] row-major. Parameters are
+ * FP32 master values; forward and backward use their BF16 roundings with FP32
+ * arithmetic. Training minimises the weighted mean squared error
+ * sum_{b,o} w_o (y_bo - t_bo)^2 / (B n_out) with AdamW (beta1 0.9,
+ * beta2 0.999, eps 1e-8, decoupled weight decay). Every reduction runs in a
+ * fixed order, so results are bitwise reproducible.
+ * Flat parameter order: W1, b1, W2, b2, W3, b3.
+ */
+#ifndef CORR_MLP_H
+#define CORR_MLP_H
+
+#include <stdint.h>
+
+#include "corr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct prop_mlp prop_mlp;
+
+/* Create a network (n_in, n_hidden <= 1024, n_out <= 64, batch size up to
+ * 4096 per call); weights Glorot-uniform from Philox4x64-10 with `seed`,
+ * biases 0, AdamW moments 0. */
+int prop_mlp_create(corr_ctx* ctx, int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed, prop_mlp** out);
+
+/* Number of parameters (FP32 master values). */
+int prop_mlp_num_params(prop_mlp* m, int64_t* n);
+
+/* Copy the FP32 master parameters out of / into the network (HOST arrays of
+ * prop_mlp_num_params floats). Setting resets nothing else. */
+int prop_mlp_get_params(prop_mlp* m, float* params);
+int prop_mlp_set_params(prop_mlp* m, const float* params);
+
+/* Forward pass: x device [B][n_in] -> y device [B][n_out]. */
+int prop_mlp_forward(prop_mlp* m, const float* x, int32_t B, float* y, corr_stream_t stream);
+
+/* One training step on a batch: forward, weighted-MSE gradient (loss_w HOST
+ * [n_out] or NULL for all ones), backward, AdamW update of the master
+ * parameters with learning rate lr and weight decay wd. loss_out (HOST,
+ * nullable; then the call synchronises) receives the batch loss before the
+ * update. */
+int prop_mlp_train_step(prop_mlp* m, const float* x, const float* target, const float* loss_w, int32_t B, float lr,
+                        float wd, float* loss_out, corr_stream_t stream);
+
+/* Gradient of the last training step (HOST, prop_mlp_num_params floats). */
+int prop_mlp_get_grads(prop_mlp* m, float* grads);
+
+/* Free the network. NULL is allowed. */
+void prop_mlp_destroy(prop_mlp* m);
+
+/*
+ * Region summaries for the proposal (n_pc + 5 floats per region, device
+ * `feats` [n_regions][n_pc + 5]): with zhat_p the centred, unit-norm member
+ * vector of grid point p and u_j the eigenvectors of the member-space Gram
+ * matrix G = (1/N) sum_p zhat_p zhat_p^T (all N points of A) ordered by
+ * decreasing eigenvalue: c_j = max over the region of |u_j . zhat_p|
+ * (j < n_pc), then the region mean of the per-point means, the region mean
+ * of the per-point standard deviations, and the region centre divided by the
+ * grid extent. evals (HOST [n_pc], nullable) receives the top eigenvalues.
+ * M <= 128, n_pc <= M. G is reduced on the GPU in a fixed order; its
+ * eigendecomposition (Jacobi) runs on the host. Synchronises `stream`.
+ */
+int corr_region_features(corr_ctx* ctx, const corr_field* A, const corr_region* regions, int32_t n_regions,
+                         int32_t n_pc, float* feats, float* evals, corr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORR_MLP_H */

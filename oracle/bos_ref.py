@@ -66,6 +66,38 @@ def philox4x64(ctr, key, rounds=10):
     return c
 
 
+def _mulhilo(a, b):
+    """64 x 64 -> (hi, lo) on numpy uint64 arrays."""
+    m32 = np.uint64(0xFFFFFFFF)
+    s32 = np.uint64(32)
+    a0, a1 = a & m32, a >> s32
+    b0, b1 = b & m32, b >> s32
+    p00, p01, p10, p11 = a0 * b0, a0 * b1, a1 * b0, a1 * b1
+    mid = (p00 >> s32) + (p01 & m32) + (p10 & m32)
+    hi = p11 + (p01 >> s32) + (p10 >> s32) + (mid >> s32)
+    return hi, a * b
+
+
+def philox4x64_np(c0, c1, c2, c3, k0, k1, rounds=10):
+    """Philox4x64 on numpy uint64 arrays (same function as philox4x64)."""
+    c0, c1, c2, c3 = (np.asarray(v, dtype=np.uint64) for v in (c0, c1, c2, c3))
+    c0, c1, c2, c3 = np.broadcast_arrays(c0, c1, c2, c3)
+    k0, k1 = np.uint64(int(k0) & MASK64), np.uint64(int(k1) & MASK64)
+    with np.errstate(over="ignore"):
+        for r in range(rounds):
+            if r:
+                k0 = np.uint64((int(k0) + PHILOX_W0) & MASK64)
+                k1 = np.uint64((int(k1) + PHILOX_W1) & MASK64)
+            hi0, lo0 = _mulhilo(np.uint64(PHILOX_M0), c0)
+            hi1, lo1 = _mulhilo(np.uint64(PHILOX_M1), c2)
+            c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return c0, c1, c2, c3
+
+
+def u01_np(w):
+    return (w >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
 def u01(w):
     return (int(w) >> 11) * (1.0 / 9007199254740992.0)
 
@@ -143,13 +175,18 @@ def candidates(cfg: BosConfig, pair: int, it: int, dims, best_cell):
     up = np.array(dims, np.float64) - 1.0
     C = cfg.n_uniform + cfg.n_local
     th = np.zeros((C, 6))
-    for c in range(cfg.n_uniform):
-        for a in range(6):
-            th[c, a] = u01(draw(cfg.seed, pair, S_UNIF, it * cfg.n_uniform + c, a)[0]) * up[a]
-    for l in range(cfg.n_local):
-        for a in range(6):
-            v = best_cell[a] + cfg.local_sd * gauss(cfg.seed, pair, S_LOCAL, it * cfg.n_local + l, a)
-            th[cfg.n_uniform + l, a] = min(max(v, 0.0), up[a])
+    key = (cfg.seed, KEY_HI)
+    ax = np.arange(6, dtype=np.uint64)[None, :]
+    if cfg.n_uniform:
+        idx = (it * cfg.n_uniform + np.arange(cfg.n_uniform, dtype=np.uint64))[:, None]
+        w = philox4x64_np(np.uint64(pair), np.uint64(S_UNIF), idx, ax, *key)
+        th[: cfg.n_uniform] = u01_np(w[0]) * up[None, :]
+    if cfg.n_local:
+        idx = (it * cfg.n_local + np.arange(cfg.n_local, dtype=np.uint64))[:, None]
+        w = philox4x64_np(np.uint64(pair), np.uint64(S_LOCAL), idx, ax, *key)
+        u1, u2 = u01_np(w[0]), u01_np(w[1])
+        z = np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * math.pi * u2)
+        th[cfg.n_uniform:] = np.clip(np.asarray(best_cell, np.float64)[None, :] + cfg.local_sd * z, 0.0, up[None, :])
     return th
 
 
@@ -184,40 +221,56 @@ def round_cell(cfg: BosConfig, pair: int, slot: int, theta, dims):
     return cell
 
 
-def run_pair(cfg: BosConfig, pair: int, dims, objective, max_iters=None, history=None):
-    """Full BOS of one region pair. objective(cells (n, 6)) -> values (n,).
+def iteration_cells(cfg: BosConfig, pair: int, it: int, dims, X, y, slot):
+    """Cells newly evaluated by batch `it` of `pair`, given its observations so far.
 
-    Returns dict(value, cell, n_evaluated, cells, values, iters) where cells /
-    values are the evaluated (unique) observations in order.
+    X (n, 6) int cells and y (n,) values are the pair's observations in
+    evaluation order; slot = n_init + samples of the earlier batches.
     """
+    b = schedule(cfg, pair)[it]
+    yt = standardize_y(np.asarray(y, np.float64))
+    best = int(np.argmax(y))
+    th = candidates(cfg, pair, it, dims, X[best])
+    picks, _ = believer_picks(cfg, np.asarray(X, np.float64), yt, th, b)
+    seen = {tuple(int(v) for v in c) for c in X}
+    new = []
+    for m, c in enumerate(picks):
+        cell = round_cell(cfg, pair, slot + m, th[c], dims)
+        t = tuple(int(v) for v in cell)
+        if t not in seen:
+            seen.add(t)
+            new.append(cell)
+    return np.array(new, np.int64).reshape(-1, 6), b
+
+
+def initial_unique_cells(cfg: BosConfig, pair: int, dims, prior_cell=None):
     init = initial_cells(cfg, pair, dims)
+    if prior_cell is not None and prior_cell[0] >= 0:
+        init[0] = [min(max(int(np.rint(v)), 0), dims[a] - 1) for a, v in enumerate(prior_cell)]
     X, seen = [], set()
     for c in init:
         t = tuple(int(v) for v in c)
         if t not in seen:
             seen.add(t)
             X.append(c)
-    X = np.array(X, np.int64)
+    return np.array(X, np.int64)
+
+
+def run_pair(cfg: BosConfig, pair: int, dims, objective, max_iters=None, prior_cell=None):
+    """Full BOS of one region pair. objective(cells (n, 6)) -> values (n,).
+
+    Returns dict(value, cell, n_evaluated, cells, values, iters) where cells /
+    values are the evaluated (unique) observations in order.
+    """
+    X = initial_unique_cells(cfg, pair, dims, prior_cell)
     y = np.asarray(objective(X), np.float64)
     sched = schedule(cfg, pair)
     slot = cfg.n_init
     n_it = len(sched) if max_iters is None else min(max_iters, len(sched))
     for it in range(n_it):
-        b = sched[it]
-        yt = standardize_y(y)
-        best = int(np.argmax(y))
-        th = candidates(cfg, pair, it, dims, X[best])
-        picks, _ = believer_picks(cfg, X.astype(np.float64), yt, th, b)
-        new = []
-        for m, c in enumerate(picks):
-            cell = round_cell(cfg, pair, slot + m, th[c], dims)
-            t = tuple(int(v) for v in cell)
-            if t not in seen:
-                seen.add(t)
-                new.append(cell)
+        new, b = iteration_cells(cfg, pair, it, dims, X, y, slot)
         slot += b
-        if new:
-            new = np.array(new, np.int64)
+        if new.shape[0]:
             X = np.vstack([X, new])
             y = np.concatenate([y, np.asarray(objective(new), np.float64)])
     best = int(np.argmax(y))

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import CorrError, corr_field, corr_max, corr_region, PREC, MEASURE  # noqa: F401
+from ._lib import CorrError, bos_config, corr_field, corr_max, corr_region, PREC, MEASURE  # noqa: F401
 
 
 def _torch():
@@ -165,6 +165,169 @@ class Context:
                                           ctypes.byref(out), _stream_ptr(stream)))
         return dict(value=out.value, signed_value=out.signed_value, pa=out.pa, pb=out.pb,
                     n_evaluated=out.n_evaluated)
+
+
+def bos_defaults(**overrides) -> bos_config:
+    """bos_config with the library defaults, then the given fields."""
+    c = bos_config()
+    _lib.load().bos_config_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        if k == "measure" and isinstance(v, str):
+            v = MEASURE[v]
+        setattr(c, k, v)
+    return c
+
+
+class Bos:
+    """Batched Bayesian optimal sampling of region-pair maxima (include/bos.h)."""
+
+    def __init__(self, ctx: Context, A: Field, regions, region_pairs, cfg: bos_config = None, B: Field = None,
+                 stream=None):
+        import numpy as np
+        self.ctx, self.A = ctx, A
+        self.B = A if B is None else B
+        self.L = ctx.L
+        cfg = bos_defaults() if cfg is None else cfg
+        self.cfg = cfg
+        regs = (corr_region * len(regions))(*[r if isinstance(r, corr_region) else region(*r) for r in regions])
+        self._regs = regs
+        rp = np.ascontiguousarray(np.asarray(region_pairs, dtype=np.int32).reshape(-1, 2))
+        self.n_pairs = rp.shape[0]
+        self.region_pairs = rp
+        h = ctypes.c_void_p()
+        _lib.check(self.L.bos_create(ctx.h, ctypes.byref(A.c), ctypes.byref(self.B.c), regs, len(regions),
+                                     ctypes.c_void_p(rp.ctypes.data), self.n_pairs, ctypes.byref(cfg),
+                                     ctypes.byref(h), _stream_ptr(stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.bos_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bos_set_prior(self, cells):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.float32).reshape(self.n_pairs, 6))
+        _lib.check(self.L.bos_set_prior(self.h, ctypes.c_void_p(c.ctypes.data)))
+
+    def bos_sample_step(self, stream=None) -> int:
+        n = ctypes.c_int32()
+        _lib.check(self.L.bos_sample_step(self.h, _stream_ptr(stream), ctypes.byref(n)))
+        return int(n.value)
+
+    def bos_run(self, stream=None):
+        _lib.check(self.L.bos_run(self.h, _stream_ptr(stream)))
+
+    def bos_results(self, stream=None):
+        out = (corr_max * self.n_pairs)()
+        _lib.check(self.L.bos_results(self.h, out, _stream_ptr(stream)))
+        return [dict(value=o.value, signed_value=o.signed_value, pa=o.pa, pb=o.pb, n_evaluated=o.n_evaluated)
+                for o in out]
+
+    def bos_history(self, pair: int, stream=None):
+        import numpy as np
+        nt = self.cfg.n_total
+        cells = np.zeros((nt, 6), np.int32)
+        vals = np.zeros(nt, np.float32)
+        n = ctypes.c_int32()
+        _lib.check(self.L.bos_history(self.h, int(pair), ctypes.c_void_p(cells.ctypes.data),
+                                      ctypes.c_void_p(vals.ctypes.data), ctypes.byref(n), _stream_ptr(stream)))
+        return cells[: n.value].copy(), vals[: n.value].copy()
+
+    def bos_save(self, path: str, stream=None):
+        _lib.check(self.L.bos_save(self.h, path.encode(), _stream_ptr(stream)))
+
+    def bos_load(self, path: str, stream=None):
+        _lib.check(self.L.bos_load(self.h, path.encode(), _stream_ptr(stream)))
+
+
+class PropMlp:
+    """Learned BOS proposal network (include/mlp.h)."""
+
+    def __init__(self, ctx: Context, n_in: int = 42, n_hidden: int = 256, n_out: int = 8, seed: int = 1):
+        self.ctx, self.L = ctx, ctx.L
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        h = ctypes.c_void_p()
+        _lib.check(self.L.prop_mlp_create(ctx.h, n_in, n_hidden, n_out, ctypes.c_uint64(seed), ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        _lib.check(self.L.prop_mlp_num_params(self.h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.prop_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.n_params, np.float32)
+        _lib.check(self.L.prop_mlp_get_params(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(np.asarray(params, np.float32).reshape(self.n_params))
+        _lib.check(self.L.prop_mlp_set_params(self.h, ctypes.c_void_p(p.ctypes.data)))
+
+    def get_grads(self):
+        import numpy as np
+        out = np.zeros(self.n_params, np.float32)
+        _lib.check(self.L.prop_mlp_get_grads(self.h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        torch = _torch()
+        x = x.contiguous()
+        if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 2 or x.shape[1] != self.n_in:
+            raise ValueError("x must be a float32 device tensor (B, n_in)")
+        y = out if out is not None else torch.empty(x.shape[0], self.n_out, device=x.device, dtype=torch.float32)
+        _lib.check(self.L.prop_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                           ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def train_step(self, x, target, lr=1e-3, wd=1e-4, loss_w=None, stream=None) -> float:
+        import numpy as np
+        torch = _torch()
+        x, target = x.contiguous(), target.contiguous()
+        if x.dtype != torch.float32 or target.dtype != torch.float32 or not x.is_cuda or not target.is_cuda:
+            raise ValueError("x and target must be float32 device tensors")
+        if x.dim() != 2 or x.shape[1] != self.n_in or tuple(target.shape) != (x.shape[0], self.n_out):
+            raise ValueError("x (B, n_in) and target (B, n_out) expected")
+        wp = None
+        if loss_w is not None:
+            w = np.ascontiguousarray(np.asarray(loss_w, np.float32).reshape(self.n_out))
+            wp = ctypes.c_void_p(w.ctypes.data)
+        loss = ctypes.c_float()
+        _lib.check(self.L.prop_mlp_train_step(self.h, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(target.data_ptr()), wp, x.shape[0], float(lr),
+                                              float(wd), ctypes.byref(loss), _stream_ptr(stream)))
+        return float(loss.value)
+
+
+def corr_region_features(ctx: Context, A: Field, regions, n_pc: int = 16, stream=None):
+    """Per-region summaries (n_regions, n_pc + 5) on the device and the top eigenvalues (host)."""
+    import numpy as np
+    torch = _torch()
+    regs = (corr_region * len(regions))(*[r if isinstance(r, corr_region) else region(*r) for r in regions])
+    feats = torch.empty(len(regions), n_pc + 5, device=A.data.device, dtype=torch.float32)
+    ev = np.zeros(n_pc, np.float32)
+    _lib.check(ctx.L.corr_region_features(ctx.h, ctypes.byref(A.c), regs, len(regions), int(n_pc),
+                                          ctypes.c_void_p(feats.data_ptr()), ctypes.c_void_p(ev.ctypes.data),
+                                          _stream_ptr(stream)))
+    return feats, ev
 
 
 def version() -> str:

@@ -36,6 +36,13 @@ class corr_max(ctypes.Structure):
                 ("pb", ctypes.c_int32), ("n_evaluated", ctypes.c_int64)]
 
 
+class bos_config(ctypes.Structure):
+    _fields_ = [("measure", ctypes.c_int32), ("k", ctypes.c_int32), ("n_init", ctypes.c_int32),
+                ("n_total", ctypes.c_int32), ("n_uniform", ctypes.c_int32), ("n_local", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("lengthscale", ctypes.c_double), ("local_sd", ctypes.c_double),
+                ("jitter", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 class CorrError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"libcorr status {status}: {msg}")
@@ -65,7 +72,29 @@ SIGNATURES = {
     "corr_tune_save": (_I, [_P, ctypes.c_char_p]),
     "corr_tune_load": (_I, [_P, ctypes.c_char_p]),
     "corr_set_timing": (_I, [_P, _I]),
+    "bos_config_default": (None, [ctypes.POINTER(bos_config)]),
+    "bos_create": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), ctypes.POINTER(corr_region),
+                        _I32, _P, _I32, ctypes.POINTER(bos_config), ctypes.POINTER(_P), _P]),
+    "bos_set_prior": (_I, [_P, _P]),
+    "bos_sample_step": (_I, [_P, _P, ctypes.POINTER(_I32)]),
+    "bos_run": (_I, [_P, _P]),
+    "bos_results": (_I, [_P, ctypes.POINTER(corr_max), _P]),
+    "bos_history": (_I, [_P, _I32, _P, _P, ctypes.POINTER(_I32), _P]),
+    "bos_save": (_I, [_P, ctypes.c_char_p, _P]),
+    "bos_load": (_I, [_P, ctypes.c_char_p, _P]),
+    "bos_destroy": (None, [_P]),
     "corr_kernel_time_ms": (_I, [_P, _I, ctypes.POINTER(ctypes.c_float)]),
+    "prop_mlp_create": (_I, [_P, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "prop_mlp_num_params": (_I, [_P, ctypes.POINTER(_I64)]),
+    "prop_mlp_get_params": (_I, [_P, _P]),
+    "prop_mlp_set_params": (_I, [_P, _P]),
+    "prop_mlp_forward": (_I, [_P, _P, _I32, _P, _P]),
+    "prop_mlp_train_step": (_I, [_P, _P, _P, _P, _I32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.POINTER(ctypes.c_float), _P]),
+    "prop_mlp_get_grads": (_I, [_P, _P]),
+    "prop_mlp_destroy": (None, [_P]),
+    "corr_region_features": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I32, _I32, _P, _P,
+                                  _P]),
 }
 
 

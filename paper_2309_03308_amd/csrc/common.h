@@ -211,4 +211,46 @@ __host__ __device__ inline uint32_t key_lin(unsigned long long key) {
     return 0x7fffffffu - (uint32_t)((key >> 1) & 0x7fffffffu);
 }
 
+// ------------------------------------------------------------------ Philox
+constexpr uint64_t PH_M0 = 0xD2E7470EE14C6C93ull, PH_M1 = 0xCA5A826395121157ull;
+constexpr uint64_t PH_W0 = 0x9E3779B97F4A7C15ull, PH_W1 = 0xBB67AE8584CAA73Bull;
+constexpr uint64_t KEY_HI = 0x636F7272ull;
+enum { ST_INIT = 0, ST_SCHED = 1, ST_UNIF = 2, ST_LOCAL = 3, ST_ROUND = 4 };
+
+// Philox4x64-10 block function (Salmon, Moraes, Dror, Shaw 2011).
+__host__ __device__ inline void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                           uint64_t k1, uint64_t out[4]) {
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += PH_W0;
+            k1 += PH_W1;
+        }
+#ifdef __HIP_DEVICE_COMPILE__
+        const uint64_t hi0 = __umul64hi(PH_M0, c0), hi1 = __umul64hi(PH_M1, c2);
+#else
+        const uint64_t hi0 = (uint64_t)(((unsigned __int128)PH_M0 * c0) >> 64);
+        const uint64_t hi1 = (uint64_t)(((unsigned __int128)PH_M1 * c2) >> 64);
+#endif
+        const uint64_t lo0 = PH_M0 * c0, lo1 = PH_M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+__host__ __device__ inline double ph_u01(uint64_t w) { return (double)(w >> 11) * (1.0 / 9007199254740992.0); }
+
+__host__ __device__ inline double ph_uniform(uint64_t seed, uint64_t pair, uint64_t stream, uint64_t index,
+                                             uint64_t axis) {
+    uint64_t o[4];
+    philox4x64(pair, stream, index, axis, seed, KEY_HI, o);
+    return ph_u01(o[0]);
+}
+
 }  // namespace corr

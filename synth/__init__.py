@@ -13,6 +13,9 @@ from .fields import (  # noqa: F401
     make_cfg2,
     make_cfg3,
     make_cfg4,
+    make_context,
+    context_regions,
+    region_pair_list,
     make_field,
     random_pairs,
     region_pairs_uniform,

@@ -202,31 +202,53 @@ def make_cfg2() -> Ensemble:
     return make_field("focus-80x32x20-M100", 2, 100, 80, 32, 20, groups, [ra, rb])
 
 
+def context_regions(ni: int, nj: int, dims=(32, 32, 20)):
+    dx, dy, dz = dims
+    return [Region(dx * i, dy * j, 0, dx, dy, dz) for j in range(nj) for i in range(ni)]
+
+
 def cfg3_regions():
-    return [Region(32 * i, 32 * j, 0, 32, 32, 20) for j in range(8) for i in range(11)]
+    return context_regions(11, 8)
 
 
-def make_cfg3(M: int = 100, seed: int = 3) -> Ensemble:
-    """352x256x20 grid, M members, 88 regions of 32x32x20, 8 planted groups of 2-3 blobs."""
-    regions = cfg3_regions()
+def make_context(ni: int, nj: int, dims=(32, 32, 20), M: int = 100, seed: int = 3, n_groups: int = 8,
+                 blob_r: float = 4.0, min_region_gap: int = 3, name: str = None) -> Ensemble:
+    """Grid of ni x nj regions (one region layer), planted groups of 2-3 blobs
+    in regions at least `min_region_gap` region steps apart (Chebyshev)."""
+    regions = context_regions(ni, nj, dims)
     rng = np.random.Generator(np.random.PCG64(10_000 + seed))
     used = set()
     groups = []
-    for g in range(8):
+    margin = int(min(blob_r, (min(dims) - 1) // 2))
+    for g in range(n_groups):
         nb = int(rng.integers(2, 4))
         chosen = []
         for _ in range(100000):
             if len(chosen) == nb:
                 break
-            r = int(rng.integers(0, 88))
-            ri, rj = r % 11, r // 11
-            if r in used or any(max(abs(ri - c % 11), abs(rj - c // 11)) < 3 for c in chosen):
+            r = int(rng.integers(0, ni * nj))
+            ri, rj = r % ni, r // ni
+            if r in used or any(max(abs(ri - c % ni), abs(rj - c // ni)) < min_region_gap for c in chosen):
                 continue
             chosen.append(r)
+        if len(chosen) < 2:
+            continue
         used.update(chosen)
-        blobs = [(*_place_centers(rng, regions[r], 1, 4, 0)[0], 4.0) for r in chosen]
+        blobs = [(*_place_centers(rng, regions[r], 1, margin, 0)[0], blob_r) for r in chosen]
         groups.append({"rho": (0.5, 0.8, 0.95)[g % 3], "blobs": blobs, "regions": chosen})
-    return make_field(f"context-352x256x20-M{M}", seed, M, 352, 256, 20, groups, regions)
+    nx, ny, nz = ni * dims[0], nj * dims[1], dims[2]
+    return make_field(name or f"context-{nx}x{ny}x{nz}-M{M}", seed, M, nx, ny, nz, groups, regions)
+
+
+def make_cfg3(M: int = 100, seed: int = 3) -> Ensemble:
+    """352x256x20 grid, M members, 88 regions of 32x32x20, 8 planted groups of 2-3 blobs."""
+    return make_context(11, 8, (32, 32, 20), M, seed, 8, 4.0, 3, f"context-352x256x20-M{M}")
+
+
+def region_pair_list(n_regions: int) -> np.ndarray:
+    """All unordered pairs (i < j) of regions, int32 (n, 2)."""
+    i, j = np.triu_indices(n_regions, 1)
+    return np.ascontiguousarray(np.stack([i, j], 1).astype(np.int32))
 
 
 def make_cfg4(stress_offset: bool = False, M: int = 1000, seed: int = 4) -> Ensemble:

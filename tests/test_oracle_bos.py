@@ -22,6 +22,14 @@ def test_philox_matches_numpy():
         assert B.philox4x64(c, key) == got
 
 
+def test_vectorised_philox_matches_scalar():
+    rng = np.random.default_rng(3)
+    c = rng.integers(0, 2**63, (50, 4), dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+    w = B.philox4x64_np(c[:, 0], c[:, 1], c[:, 2], c[:, 3], 2**64 - 5, 77)
+    for i in range(50):
+        assert [int(w[q][i]) for q in range(4)] == B.philox4x64([int(v) for v in c[i]], (2**64 - 5, 77))
+
+
 def test_matern_matches_sklearn():
     from sklearn.gaussian_process.kernels import Matern
     rng = np.random.default_rng(0)
@@ -114,3 +122,41 @@ def test_bos_finds_analytic_maximum_of_6d_normal():
         rnd.append((true_max - f(rng.integers(0, 8, (100, 6))).max()) / true_max)
     assert np.mean(errs) <= 0.05, errs
     assert np.mean(errs) <= np.mean(rnd) / 4, (errs, rnd)
+
+
+def replay_iterations(cfg, pair, dims, cells, vals):
+    """Replay a pair's recorded history batch by batch with the oracle.
+
+    Returns (matched, total): how many batches the oracle reproduces exactly
+    from the history that precedes them (stops at the first mismatch)."""
+    X0 = B.initial_unique_cells(cfg, pair, dims)
+    if not np.array_equal(X0, cells[: X0.shape[0]]):
+        return 0, len(B.schedule(cfg, pair)) + 1
+    n, slot = X0.shape[0], cfg.n_init
+    sched = B.schedule(cfg, pair)
+    matched = 1
+    for it in range(len(sched)):
+        new, b = B.iteration_cells(cfg, pair, it, dims, cells[:n], np.asarray(vals[:n], np.float64), slot)
+        k = new.shape[0]
+        if not np.array_equal(new, cells[n:n + k]):
+            return matched, len(sched) + 1
+        matched += 1
+        n += k
+        slot += b
+    assert n == cells.shape[0]
+    return matched, len(sched) + 1
+
+
+def test_replay_reproduces_an_oracle_run():
+    rng = np.random.default_rng(8)
+    dims = (6, 5, 4, 6, 5, 4)
+    w = rng.standard_normal(6)
+
+    def f(c):
+        return np.cos(np.asarray(c, float) @ w / 3.0)
+
+    cfg = B.BosConfig(seed=17)
+    for pair in range(3):
+        res = B.run_pair(cfg, pair, dims, f)
+        m, t = replay_iterations(cfg, pair, dims, res["cells"], res["values"])
+        assert m == t
