@@ -60,19 +60,30 @@ int prop_mlp_get_grads(prop_mlp* m, float* grads);
 void prop_mlp_destroy(prop_mlp* m);
 
 /*
- * Region summaries for the proposal (n_pc + 5 floats per region, device
- * `feats` [n_regions][n_pc + 5]): with zhat_p the centred, unit-norm member
- * vector of grid point p and u_j the eigenvectors of the member-space Gram
- * matrix G = (1/N) sum_p zhat_p zhat_p^T (all N points of A) ordered by
- * decreasing eigenvalue: c_j = max over the region of |u_j . zhat_p|
- * (j < n_pc), then the region mean of the per-point means, the region mean
- * of the per-point standard deviations, and the region centre divided by the
- * grid extent. evals (HOST [n_pc], nullable) receives the top eigenvalues.
- * M <= 128, n_pc <= M. G is reduced on the GPU in a fixed order; its
- * eigendecomposition (Jacobi) runs on the host. Synchronises `stream`.
+ * Inputs of the proposal network for region pairs of one field A (device
+ * x_out [n_pairs][2 (4 n_hot + 5) + n_hot^2], row-major).
+ *   zhat_p   centred, unit-norm member vector of grid point p (0 if constant)
+ *   s(p)     mean of zhat_p . zhat_q over the grid points q = p +- D e_x,
+ *            p +- D e_y, p +- D e_z that lie inside the grid (0 if none)
+ *   picks    per region, n_hot points: pick i is the first point (local
+ *            x-fastest order) with the largest s among the region's points
+ *            whose Chebyshev distance to every earlier pick exceeds r_nms;
+ *            when none qualifies the previous pick is repeated
+ *   region   per pick: s, local (x, y, z) / (extent - 1) (0 for extent 1);
+ *            then the region mean of the per-point means, the region mean of
+ *            the per-point population standard deviations, and the region
+ *            centre divided by the grid extent (x, y, z)
+ *   pair     region values of a, of b, then |zhat_{a_i} . zhat_{b_j}|,
+ *            i, j < n_hot, i outer.
+ * region_pairs is a HOST array [n_pairs][2] of indices into `regions`.
+ * hot_out (device [n_regions][n_hot] global point indices) may be NULL.
+ * 1 <= n_hot <= 8, D >= 1, r_nms >= 0, M >= 2. Per-point statistics are
+ * accumulated in FP64, dot products in FP32; every sum runs in a fixed
+ * order. Synchronises `stream` (the pair list is staged from the host).
  */
-int corr_region_features(corr_ctx* ctx, const corr_field* A, const corr_region* regions, int32_t n_regions,
-                         int32_t n_pc, float* feats, float* evals, corr_stream_t stream);
+int corr_proposal_inputs(corr_ctx* ctx, const corr_field* A, const corr_region* regions, int32_t n_regions,
+                         const int32_t* region_pairs, int32_t n_pairs, int32_t n_hot, int32_t D, int32_t r_nms,
+                         float* x_out, int32_t* hot_out, corr_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -12,12 +12,22 @@ Update: AdamW (decoupled weight decay), beta1 0.9, beta2 0.999, eps 1e-8:
 Parameters are kept as FP32 master values; the forward and backward pass use
 their BF16 roundings (round to nearest even), as the GPU kernels do.
 
-Region features (n_pc + 5 per region): c_j = max over the region's points of
-|u_j . zhat_p| for the top n_pc eigenvectors u_j of the member-space Gram
-matrix G = (1/N) sum_p zhat_p zhat_p^T of all N grid points (zhat: centred,
-unit-norm member vectors), then the region's mean of the per-point means,
-the mean of the per-point standard deviations, and the region centre divided
-by the grid extent (x, y, z).
+Proposal inputs of a region pair (built from the ensemble field alone):
+  zhat_p      centred, unit-norm member vector of grid point p (0 if constant)
+  s(p)        self-similarity: mean of zhat_p . zhat_q over the grid points
+              q = p +- D e_x, p +- D e_y, p +- D e_z inside the grid (0 if none)
+  hot spots   per region, n_hot picks; pick i is the first point (local
+              x-fastest order) maximising s among the region's points whose
+              Chebyshev distance to every earlier pick exceeds r_nms (when no
+              point qualifies, the previous pick is repeated)
+  region row  per pick: s, local (x, y, z) / (extent - 1) (0 for extent 1);
+              then the region's mean of the per-point means, mean of the
+              per-point standard deviations, and centre / grid extent
+  pair row    region row of a, region row of b, then |zhat_{a_i} . zhat_{b_j}|
+              for i, j < n_hot (i outer): 2 (4 n_hot + 5) + n_hot^2 values.
+Blob-shaped correlated structure keeps s high at range D where spatially
+smooth noise has decorrelated, so the picks locate candidate extrema and the
+cross terms say which of them pair up across the two regions.
 """
 from __future__ import annotations
 
@@ -94,25 +104,79 @@ def adamw(p, g, m, v, t, lr, wd, b1=0.9, b2=0.999, eps=1e-8):
     return p, m, v
 
 
-def region_features(data, regions, nx, ny, nz, n_pc=16):
-    """Features of each region (see the module docstring), FP64."""
-    x = np.asarray(data, np.float64)  # (M, P)
-    M, P = x.shape
+def standardize(data):
+    """FP64 mean, population sigma and zhat (M, P) of a member-major field."""
+    x = np.asarray(data, np.float64)
     mu = x.mean(0)
     d = x - mu
     q = np.sqrt((d * d).sum(0))
-    z = np.where(q > 0, d / np.where(q > 0, q, 1.0), 0.0)  # (M, P) unit columns
-    sig = np.sqrt((d * d).mean(0))
-    G = (z @ z.T) / P
-    evals, evecs = np.linalg.eigh(G)
-    U = evecs[:, ::-1][:, :n_pc]  # top n_pc
-    proj = np.abs(U.T @ z)  # (n_pc, P)
-    feats = []
+    z = np.where(q > 0, d / np.where(q > 0, q, 1.0), 0.0)
+    return mu, np.sqrt((d * d).mean(0)), z
+
+
+def self_similarity(z, nx, ny, nz, D=4):
+    """s(p) of the module docstring, FP64, shape (P,)."""
+    M = z.shape[0]
+    zz = z.reshape(M, nz, ny, nx)
+    acc = np.zeros((nz, ny, nx))
+    cnt = np.zeros((nz, ny, nx))
+    for axis in (1, 2, 3):
+        n = zz.shape[axis]
+        if D >= n:
+            continue
+        lo = [slice(None)] * 4
+        hi = [slice(None)] * 4
+        lo[axis] = slice(0, n - D)
+        hi[axis] = slice(D, n)
+        dots = (zz[tuple(lo)] * zz[tuple(hi)]).sum(0)  # pairs (p, p + D e)
+        acc[tuple(lo[1:])] += dots
+        cnt[tuple(lo[1:])] += 1
+        acc[tuple(hi[1:])] += dots
+        cnt[tuple(hi[1:])] += 1
+    return np.where(cnt > 0, acc / np.where(cnt > 0, cnt, 1), 0.0).reshape(-1)
+
+
+def hot_spots(sim, region, nx, ny, n_hot=4, r_nms=3):
+    """Global indices of the region's picks (module docstring)."""
+    idx = region.global_indices(nx, ny)
+    n = idx.size
+    loc = np.arange(n)
+    lx, ly, lz = loc % region.dx, (loc // region.dx) % region.dy, loc // (region.dx * region.dy)
+    ok = np.ones(n, bool)
+    picks = []
+    for _ in range(n_hot):
+        if not ok.any():
+            picks.append(picks[-1])
+            continue
+        v = np.where(ok, sim[idx], -np.inf)
+        i = int(np.argmax(v))  # first maximum in local order
+        picks.append(int(idx[i]))
+        ok &= np.maximum(np.maximum(np.abs(lx - lx[i]), np.abs(ly - ly[i])), np.abs(lz - lz[i])) > r_nms
+    return picks
+
+
+def proposal_inputs(data, nx, ny, nz, regions, region_pairs, n_hot=4, D=4, r_nms=3):
+    """Pair rows (n_pairs, 2 (4 n_hot + 5) + n_hot^2) and hot spots (n_regions, n_hot)."""
+    mu, sig, z = standardize(data)
+    sim = self_similarity(z, nx, ny, nz, D)
+    rows, hots = [], []
     for r in regions:
+        h = hot_spots(sim, r, nx, ny, n_hot, r_nms)
+        hots.append(h)
+        f = []
+        for p in h:
+            x, y, zc = p % nx, (p // nx) % ny, p // (nx * ny)
+            f += [sim[p], _unit(x - r.x0, r.dx), _unit(y - r.y0, r.dy), _unit(zc - r.z0, r.dz)]
         idx = r.global_indices(nx, ny)
-        c = proj[:, idx].max(1)
-        cx = (r.x0 + (r.dx - 1) / 2) / nx
-        cy = (r.y0 + (r.dy - 1) / 2) / ny
-        cz = (r.z0 + (r.dz - 1) / 2) / nz
-        feats.append(np.concatenate([c, [mu[idx].mean(), sig[idx].mean(), cx, cy, cz]]))
-    return np.array(feats), evals[::-1][:n_pc]
+        f += [mu[idx].mean(), sig[idx].mean(), (r.x0 + (r.dx - 1) / 2) / nx, (r.y0 + (r.dy - 1) / 2) / ny,
+              (r.z0 + (r.dz - 1) / 2) / nz]
+        rows.append(np.array(f))
+    out = []
+    for a, b in np.asarray(region_pairs).reshape(-1, 2):
+        cross = np.abs(z[:, hots[a]].T @ z[:, hots[b]]).ravel()
+        out.append(np.concatenate([rows[a], rows[b], cross]))
+    return np.array(out), np.array(hots, dtype=np.int64)
+
+
+def _unit(i, d):
+    return i / (d - 1) if d > 1 else 0.0

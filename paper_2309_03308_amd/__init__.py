@@ -317,17 +317,20 @@ class PropMlp:
         return float(loss.value)
 
 
-def corr_region_features(ctx: Context, A: Field, regions, n_pc: int = 16, stream=None):
-    """Per-region summaries (n_regions, n_pc + 5) on the device and the top eigenvalues (host)."""
+def corr_proposal_inputs(ctx: Context, A: Field, regions, region_pairs, n_hot: int = 4, D: int = 4, r_nms: int = 3,
+                         stream=None):
+    """Proposal-network inputs (n_pairs, 2 (4 n_hot + 5) + n_hot^2) and the picks (n_regions, n_hot), on the device."""
     import numpy as np
     torch = _torch()
     regs = (corr_region * len(regions))(*[r if isinstance(r, corr_region) else region(*r) for r in regions])
-    feats = torch.empty(len(regions), n_pc + 5, device=A.data.device, dtype=torch.float32)
-    ev = np.zeros(n_pc, np.float32)
-    _lib.check(ctx.L.corr_region_features(ctx.h, ctypes.byref(A.c), regs, len(regions), int(n_pc),
-                                          ctypes.c_void_p(feats.data_ptr()), ctypes.c_void_p(ev.ctypes.data),
-                                          _stream_ptr(stream)))
-    return feats, ev
+    rp = np.ascontiguousarray(np.asarray(region_pairs, dtype=np.int32).reshape(-1, 2))
+    width = 2 * (4 * n_hot + 5) + n_hot * n_hot
+    x = torch.empty(rp.shape[0], width, device=A.data.device, dtype=torch.float32)
+    hot = torch.empty(len(regions), n_hot, device=A.data.device, dtype=torch.int32)
+    _lib.check(ctx.L.corr_proposal_inputs(ctx.h, ctypes.byref(A.c), regs, len(regions), ctypes.c_void_p(rp.ctypes.data),
+                                          rp.shape[0], int(n_hot), int(D), int(r_nms), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(hot.data_ptr()), _stream_ptr(stream)))
+    return x, hot
 
 
 def version() -> str:

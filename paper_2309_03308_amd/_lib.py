@@ -93,8 +93,8 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_float), _P]),
     "prop_mlp_get_grads": (_I, [_P, _P]),
     "prop_mlp_destroy": (None, [_P]),
-    "corr_region_features": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I32, _I32, _P, _P,
-                                  _P]),
+    "corr_proposal_inputs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I32, _P, _I32, _I32,
+                                  _I32, _I32, _P, _P, _P]),
 }
 
 

@@ -1,5 +1,6 @@
-// Learned BOS proposal: a small MLP (forward, backward, AdamW) and the region
-// summaries it reads. FP32 arithmetic on BF16-rounded weights; every sum runs
+// Learned BOS proposal: a small MLP (forward, backward, AdamW) and the
+// region-pair inputs it reads (self-similarity hot spots and their cross
+// correlations). FP32 arithmetic on BF16-rounded weights; every sum runs
 // in a fixed order (no floating-point atomics), so runs are reproducible.
 //
 // The network is tiny (about 8e4 parameters); its layers are plain row-major
@@ -123,89 +124,127 @@ __global__ void adamw_kernel(float* __restrict__ p, const float* __restrict__ g,
     p[i] = p[i] - lr * (mh / (sqrtf(vh) + 1e-8f) + wd * p[i]);
 }
 
-// ---------------------------------------------------------------- features
-// Partial member-space Gram matrices over chunks of points. Block (c, t)
-// accumulates entries e = 4096 t + threadIdx.x + 256 q (q < 16) of the M x M
-// matrix over chunk c of the points, in point order.
-constexpr int GRAM_E = 16;
-__global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restrict__ Z, int64_t ld, int64_t P, int M,
-                                                           int64_t chunk, float* __restrict__ partial) {
-    __shared__ float zs[16 * 128];
-    const int MM = M * M;
-    const int ebase = blockIdx.y * (256 * GRAM_E) + threadIdx.x;
-    float acc[GRAM_E];
-    int ri[GRAM_E], ci[GRAM_E];
+// ---------------------------------------------------------------- proposal inputs
+template <typename T>
+__device__ __forceinline__ float ldv(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ float ldv<float>(const float* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ float ldv<__half>(const __half* p, int64_t i) { return __half2float(p[i]); }
+
+// s(p): one thread per grid point; member rows of the member-major field are
+// read coalesced (neighbours at +-D along x share cache lines).
+template <typename T>
+__global__ __launch_bounds__(256) void self_sim_kernel(const T* __restrict__ x, int64_t stride, int M, int nx, int ny,
+                                                       int nz, int D, const float* __restrict__ mu,
+                                                       const float* __restrict__ rs, float* __restrict__ sim) {
+    const int64_t P = (int64_t)nx * ny * nz;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int px = (int)(p % nx), py = (int)((p / nx) % ny), pz = (int)(p / ((int64_t)nx * ny));
+    int64_t q[6];
+    bool ok[6];
+    ok[0] = px + D < nx;  q[0] = p + D;
+    ok[1] = px - D >= 0;  q[1] = p - D;
+    ok[2] = py + D < ny;  q[2] = p + (int64_t)D * nx;
+    ok[3] = py - D >= 0;  q[3] = p - (int64_t)D * nx;
+    ok[4] = pz + D < nz;  q[4] = p + (int64_t)D * nx * ny;
+    ok[5] = pz - D >= 0;  q[5] = p - (int64_t)D * nx * ny;
+    float mq[6], acc[6];
 #pragma unroll
-    for (int q = 0; q < GRAM_E; ++q) {
-        acc[q] = 0.0f;
-        const int e = min(ebase + 256 * q, MM - 1);
-        ri[q] = e / M;
-        ci[q] = e - ri[q] * M;
+    for (int t = 0; t < 6; ++t) {
+        if (!ok[t]) q[t] = p;
+        mq[t] = mu[q[t]];
+        acc[t] = 0.0f;
     }
-    const int64_t p0 = (int64_t)blockIdx.x * chunk;
-    const int64_t p1 = min(P, p0 + chunk);
-    for (int64_t pb = p0; pb < p1; pb += 16) {
-        const int np = (int)min((int64_t)16, p1 - pb);
-        for (int e = threadIdx.x; e < 16 * M; e += 256) {
-            const int r = e / M, c = e - r * M;
-            zs[e] = r < np ? Z[(pb + r) * ld + c] : 0.0f;
+    const float mp = mu[p];
+    for (int m = 0; m < M; ++m) {
+        const T* row = x + (int64_t)m * stride;
+        const float dp = ldv(row, p) - mp;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc[t] = fmaf(dp, ldv(row, q[t]) - mq[t], acc[t]);
+    }
+    float sum = 0.0f;
+    int cnt = 0;
+    const float rp = rs[p];
+#pragma unroll
+    for (int t = 0; t < 6; ++t)
+        if (ok[t]) {
+            sum += acc[t] * rp * rs[q[t]];
+            ++cnt;
         }
-        __syncthreads();
-        for (int r = 0; r < np; ++r) {
-            const float* z = zs + r * M;
-#pragma unroll
-            for (int q = 0; q < GRAM_E; ++q) acc[q] = fmaf(z[ri[q]], z[ci[q]], acc[q]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < GRAM_E; ++q) {
-        const int e = ebase + 256 * q;
-        if (e < MM) partial[(int64_t)blockIdx.x * MM + e] = acc[q];
-    }
+    sim[p] = cnt ? sum / (float)cnt : 0.0f;
 }
 
-__global__ void gram_reduce_kernel(const float* __restrict__ partial, int nchunks, int MM, double* __restrict__ G,
-                                   double scale) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= MM) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += (double)partial[(int64_t)c * MM + e];
-    G[e] = s * scale;
-}
-
-// One block per region: max |u_j . zhat_p|, mean of mu, mean of sigma
-__global__ __launch_bounds__(256) void region_feat_kernel(const float* __restrict__ Z, int64_t ld, int M,
-                                                          const float* __restrict__ U, int n_pc,
-                                                          const Box* __restrict__ boxes,
-                                                          const float* __restrict__ mu32,
-                                                          const float* __restrict__ sigma, int nz,
-                                                          float* __restrict__ feats) {
-    __shared__ float us[128 * 32];
-    __shared__ float red[256 * 2];
-    __shared__ float mx[256];
+// One block per region: n_hot suppressed argmax rounds over s, then the
+// region's row (picks, mean of mu, mean of sigma, centre).
+__global__ __launch_bounds__(256) void hot_spot_kernel(const float* __restrict__ sim, const Box* __restrict__ boxes,
+                                                       int n_hot, int r_nms, int nz, const float* __restrict__ mu,
+                                                       const float* __restrict__ sigma, int32_t* __restrict__ hot,
+                                                       float* __restrict__ rows) {
+    __shared__ float bv[256];
+    __shared__ int bi[256];
+    __shared__ int picks[8][3];
+    __shared__ float red[512];
     const int r = blockIdx.x;
     const Box bx = boxes[r];
-    for (int e = threadIdx.x; e < n_pc * M; e += 256) us[e] = U[e];
-    __syncthreads();
-    float cmax[32];
-#pragma unroll
-    for (int j = 0; j < 32; ++j) cmax[j] = 0.0f;
-    float smu = 0.0f, ssg = 0.0f;
-    const int64_t cnt = bx.count();
-    for (int64_t i = threadIdx.x; i < cnt; i += 256) {
-        const int64_t p = bx.global(i);
-        const float* z = Z + p * ld;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            if (j < n_pc) {
-                float s = 0.0f;
-                for (int m = 0; m < M; ++m) s = fmaf(us[j * M + m], z[m], s);
-                cmax[j] = fmaxf(cmax[j], fabsf(s));
+    const int cnt = (int)bx.count();
+    const int F = 4 * n_hot + 5;
+    float* row = rows + (int64_t)r * F;
+    int prev = 0;
+    for (int h = 0; h < n_hot; ++h) {
+        float best = -INFINITY;
+        int besti = 0x7fffffff;
+        for (int i = threadIdx.x; i < cnt; i += 256) {
+            const int lx = i % bx.dx, ly = (i / bx.dx) % bx.dy, lz = i / (bx.dx * bx.dy);
+            bool ok = true;
+            for (int g = 0; g < h; ++g) {
+                const int dx = abs(lx - picks[g][0]), dy = abs(ly - picks[g][1]), dz = abs(lz - picks[g][2]);
+                if (max(dx, max(dy, dz)) <= r_nms) ok = false;
+            }
+            if (ok) {
+                const float v = sim[bx.global(i)];
+                if (v > best) {  // ascending i: this thread's first maximum
+                    best = v;
+                    besti = i;
+                }
             }
         }
-        smu += mu32[p];
-        ssg += sigma[p];
+        bv[threadIdx.x] = best;
+        bi[threadIdx.x] = besti;
+        __syncthreads();
+        for (int st = 128; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) {
+                const float o = bv[threadIdx.x + st];
+                const int oi = bi[threadIdx.x + st];
+                if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+                    bv[threadIdx.x] = o;
+                    bi[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int i = bi[0] == 0x7fffffff ? prev : bi[0];  // nothing eligible: repeat
+            prev = i;
+            const int lx = i % bx.dx, ly = (i / bx.dx) % bx.dy, lz = i / (bx.dx * bx.dy);
+            picks[h][0] = lx;
+            picks[h][1] = ly;
+            picks[h][2] = lz;
+            const int g = bx.global(i);
+            hot[(int64_t)r * n_hot + h] = g;
+            row[4 * h + 0] = sim[g];
+            row[4 * h + 1] = bx.dx > 1 ? (float)lx / (float)(bx.dx - 1) : 0.0f;
+            row[4 * h + 2] = bx.dy > 1 ? (float)ly / (float)(bx.dy - 1) : 0.0f;
+            row[4 * h + 3] = bx.dz > 1 ? (float)lz / (float)(bx.dz - 1) : 0.0f;
+        }
+        __syncthreads();
+    }
+    float smu = 0.0f, ssg = 0.0f;
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        const int g = bx.global(i);
+        smu += mu[g];
+        ssg += sigma[g];
     }
     red[threadIdx.x] = smu;
     red[256 + threadIdx.x] = ssg;
@@ -217,68 +256,74 @@ __global__ __launch_bounds__(256) void region_feat_kernel(const float* __restric
         }
         __syncthreads();
     }
-    const int F = n_pc + 5;
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-        if (j < n_pc) {  // uniform over the block
-            mx[threadIdx.x] = cmax[j];
-            __syncthreads();
-            for (int st = 128; st >= 1; st >>= 1) {
-                if ((int)threadIdx.x < st) mx[threadIdx.x] = fmaxf(mx[threadIdx.x], mx[threadIdx.x + st]);
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) feats[(int64_t)r * F + j] = mx[0];
-            __syncthreads();
-        }
-    }
     if (threadIdx.x == 0) {
-        feats[(int64_t)r * F + n_pc] = red[0] / (float)cnt;
-        feats[(int64_t)r * F + n_pc + 1] = red[256] / (float)cnt;
-        feats[(int64_t)r * F + n_pc + 2] = (float)((bx.x0 + (bx.dx - 1) * 0.5) / bx.nx);
-        feats[(int64_t)r * F + n_pc + 3] = (float)((bx.y0 + (bx.dy - 1) * 0.5) / bx.ny);
-        feats[(int64_t)r * F + n_pc + 4] = (float)((bx.z0 + (bx.dz - 1) * 0.5) / nz);
+        float* o = row + 4 * n_hot;
+        o[0] = red[0] / (float)cnt;
+        o[1] = red[256] / (float)cnt;
+        o[2] = (float)((bx.x0 + (bx.dx - 1) * 0.5) / bx.nx);
+        o[3] = (float)((bx.y0 + (bx.dy - 1) * 0.5) / bx.ny);
+        o[4] = (float)((bx.z0 + (bx.dz - 1) * 0.5) / nz);
     }
 }
 
-// Cyclic Jacobi eigendecomposition of a symmetric n x n matrix (row-major,
-// overwritten); V receives the eigenvectors as columns.
-static void jacobi_eigen(std::vector<double>& A, int n, std::vector<double>& V, std::vector<double>& w) {
-    V.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-    auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-    double scale = 0.0;
-    for (int i = 0; i < n; ++i) scale += a(i, i) * a(i, i);
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) off += a(p, q) * a(p, q);
-        if (off <= 1e-30 * (scale + 1e-300)) break;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = a(p, q);
-                if (std::fabs(apq) < 1e-300) continue;
-                const double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < n; ++k) {  // columns p, q
-                    const double akp = a(k, p), akq = a(k, q);
-                    a(k, p) = c * akp - s * akq;
-                    a(k, q) = s * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {  // rows p, q
-                    const double apk = a(p, k), aqk = a(q, k);
-                    a(p, k) = c * apk - s * aqk;
-                    a(q, k) = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = c * vkp - s * vkq;
-                    V[(size_t)k * n + q] = s * vkp + c * vkq;
-                }
-            }
+// One wave per region pair: the two region rows, then |zhat_a_i . zhat_b_j|
+// with members over lanes and a fixed xor-tree reduction.
+template <typename T>
+__global__ __launch_bounds__(256) void pair_row_kernel(const T* __restrict__ x, int64_t stride, int M,
+                                                       const float* __restrict__ mu, const float* __restrict__ rs,
+                                                       const int32_t* __restrict__ hot, const float* __restrict__ rows,
+                                                       const int32_t* __restrict__ rpairs, int n_pairs, int n_hot,
+                                                       float* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int pr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pr >= n_pairs) return;
+    const int ra = rpairs[2 * pr], rb = rpairs[2 * pr + 1];
+    const int F = 4 * n_hot + 5;
+    const int W = 2 * F + n_hot * n_hot;
+    float* o = out + (int64_t)pr * W;
+    for (int t = lane; t < F; t += 64) {
+        o[t] = rows[(int64_t)ra * F + t];
+        o[F + t] = rows[(int64_t)rb * F + t];
     }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = a(i, i);
+    int ha[8], hb[8];
+    float mua[8], mub[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        ha[i] = i < n_hot ? hot[(int64_t)ra * n_hot + i] : 0;
+        hb[i] = i < n_hot ? hot[(int64_t)rb * n_hot + i] : 0;
+        mua[i] = mu[ha[i]];
+        mub[i] = mu[hb[i]];
+    }
+    float acc[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) acc[e] = 0.0f;
+    for (int m = lane; m < M; m += 64) {
+        const T* row = x + (int64_t)m * stride;
+        float va[8], vb[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            va[i] = i < n_hot ? ldv(row, ha[i]) - mua[i] : 0.0f;
+            vb[i] = i < n_hot ? ldv(row, hb[i]) - mub[i] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[8 * i + j] = fmaf(va[i], vb[j], acc[8 * i + j]);
+    }
+#pragma unroll
+    for (int e = 0; e < 64; ++e) {
+        float v = acc[e];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        acc[e] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (i < n_hot && j < n_hot) o[2 * F + i * n_hot + j] = fabsf(acc[8 * i + j] * rs[ha[i]] * rs[hb[j]]);
+    }
 }
 
 }  // namespace corr
@@ -483,68 +528,74 @@ int prop_mlp_train_step(prop_mlp* mm, const float* x, const float* target, const
     return CORR_OK;
 }
 
-int corr_region_features(corr_ctx* ctx, const corr_field* A, const corr_region* regions, int32_t n_regions,
-                         int32_t n_pc, float* feats, float* evals, corr_stream_t stream) {
-    if (!ctx || !A || !regions || !feats) return fail(CORR_EINVAL, "corr_region_features: null argument");
-    if (!A->data || (A->dtype != CORR_F32 && A->dtype != CORR_F16)) return fail(CORR_EINVAL, "corr_region_features: field");
-    if (A->M < 2 || A->M > 128) return fail(CORR_EUNSUPPORTED, "corr_region_features: M must be in [2, 128]");
-    if (n_pc < 1 || n_pc > A->M || n_pc > 32) return fail(CORR_EINVAL, "corr_region_features: n_pc");
-    if (n_regions < 1) return fail(CORR_EINVAL, "corr_region_features: no regions");
+int corr_proposal_inputs(corr_ctx* ctx, const corr_field* A, const corr_region* regions, int32_t n_regions,
+                         const int32_t* region_pairs, int32_t n_pairs, int32_t n_hot, int32_t D, int32_t r_nms,
+                         float* x_out, int32_t* hot_out, corr_stream_t stream) {
+    if (!ctx || !A || !regions || !region_pairs || !x_out)
+        return fail(CORR_EINVAL, "corr_proposal_inputs: null argument");
+    if (!A->data || (A->dtype != CORR_F32 && A->dtype != CORR_F16) || A->nx < 1 || A->ny < 1 || A->nz < 1)
+        return fail(CORR_EINVAL, "corr_proposal_inputs: field");
+    if (A->M < 2) return fail(CORR_EINVAL, "corr_proposal_inputs: M must be at least 2");
+    if (n_hot < 1 || n_hot > 8 || D < 1 || r_nms < 0) return fail(CORR_EINVAL, "corr_proposal_inputs: n_hot / D / r_nms");
+    if (n_regions < 1 || n_pairs < 0) return fail(CORR_EINVAL, "corr_proposal_inputs: region / pair counts");
+    const int64_t P = (int64_t)A->nx * A->ny * A->nz;
+    if (P > INT32_MAX) return fail(CORR_EUNSUPPORTED, "corr_proposal_inputs: grid too large");
     for (int r = 0; r < n_regions; ++r) {
         const corr_region& g = regions[r];
         if (g.dx < 1 || g.dy < 1 || g.dz < 1 || g.x0 < 0 || g.y0 < 0 || g.z0 < 0 || g.x0 + g.dx > A->nx ||
             g.y0 + g.dy > A->ny || g.z0 + g.dz > A->nz)
-            return fail(CORR_EINVAL, "corr_region_features: region outside the grid");
+            return fail(CORR_EINVAL, "corr_proposal_inputs: region outside the grid");
     }
+    for (int64_t i = 0; i < 2 * (int64_t)n_pairs; ++i)
+        if (region_pairs[i] < 0 || region_pairs[i] >= n_regions)
+            return fail(CORR_EINVAL, "corr_proposal_inputs: region pair index out of range");
     hipStream_t s = (hipStream_t)stream;
-    const int M = A->M;
     const Box whole{0, 0, 0, A->nx, A->ny, A->nz, A->nx, A->ny};
-    const int64_t P = whole.count();
-    const int64_t ld = (M + 3) / 4 * 4;
-    void *sb, *zb, *pb, *gb, *ub, *bb;
+    const int F = 4 * n_hot + 5;
+    void *sb, *simb, *mb;
     int rc = ws_get(ctx, WS_STATS_A, sizeof(float) * 4 * (size_t)P, s, &sb);
     if (rc) return rc;
     Stats st = stats_view((float*)sb, P);
     if ((rc = launch_stats(*A, whole, true, st, s))) return rc;
-    if ((rc = ws_get(ctx, WS_ZH_A, sizeof(float) * (size_t)(P * ld), s, &zb))) return rc;
-    if ((rc = launch_transpose(*A, whole, st, ZF_F32, zb, nullptr, P, ld, s))) return rc;
-    const int64_t chunk = 2048;
-    const int nchunks = (int)((P + chunk - 1) / chunk);
-    const int MM = M * M;
-    if ((rc = ws_get(ctx, WS_MISC, sizeof(float) * (size_t)nchunks * MM, s, &pb))) return rc;
-    if ((rc = ws_get(ctx, WS_PAIRS, sizeof(double) * (size_t)MM + sizeof(float) * 32 * 128 +
-                                         sizeof(Box) * (size_t)n_regions + 1024,
-                     s, &gb)))
-        return rc;
-    gram_partial_kernel<<<dim3(nchunks, (MM + 256 * GRAM_E - 1) / (256 * GRAM_E)), 256, 0, s>>>((const float*)zb, ld, P, M, chunk, (float*)pb);
-    gram_reduce_kernel<<<dim3((MM + 255) / 256), 256, 0, s>>>((const float*)pb, nchunks, MM, (double*)gb,
-                                                              1.0 / (double)P);
-    CORR_LAUNCH_CHECK();
-    std::vector<double> G(MM);
-    CORR_HIP(hipMemcpyAsync(G.data(), gb, sizeof(double) * MM, hipMemcpyDeviceToHost, s));
-    CORR_HIP(hipStreamSynchronize(s));
-    std::vector<double> V, w;
-    jacobi_eigen(G, M, V, w);
-    std::vector<int> order(M);
-    for (int i = 0; i < M; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
-    std::vector<float> U((size_t)n_pc * M);
-    for (int j = 0; j < n_pc; ++j)
-        for (int m = 0; m < M; ++m) U[(size_t)j * M + m] = (float)V[(size_t)m * M + order[j]];
-    if (evals)
-        for (int j = 0; j < n_pc; ++j) evals[j] = (float)w[order[j]];
-    ub = (char*)gb + sizeof(double) * MM;
-    bb = (char*)ub + sizeof(float) * 32 * 128;
-    std::vector<Box> boxes(n_regions);
+    if ((rc = ws_get(ctx, WS_MISC, sizeof(float) * (size_t)P, s, &simb))) return rc;
+    const size_t hot_bytes = sizeof(int32_t) * (size_t)n_regions * n_hot;
+    const size_t row_bytes = sizeof(float) * (size_t)n_regions * F;
+    const size_t box_bytes = sizeof(Box) * (size_t)n_regions;
+    const size_t pr_bytes = sizeof(int32_t) * 2 * (size_t)n_pairs;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    if ((rc = ws_get(ctx, WS_PAIRS, al(hot_bytes) + al(row_bytes) + al(box_bytes) + al(pr_bytes), s, &mb))) return rc;
+    int32_t* hot = (int32_t*)mb;
+    float* rows = (float*)((char*)mb + al(hot_bytes));
+    Box* boxes = (Box*)((char*)rows + al(row_bytes));
+    int32_t* rp = (int32_t*)((char*)boxes + al(box_bytes));
+    std::vector<Box> hb(n_regions);
     for (int r = 0; r < n_regions; ++r) {
         const corr_region& g = regions[r];
-        boxes[r] = Box{g.x0, g.y0, g.z0, g.dx, g.dy, g.dz, A->nx, A->ny};
+        hb[r] = Box{g.x0, g.y0, g.z0, g.dx, g.dy, g.dz, A->nx, A->ny};
     }
-    CORR_HIP(hipMemcpyAsync(ub, U.data(), sizeof(float) * U.size(), hipMemcpyHostToDevice, s));
-    CORR_HIP(hipMemcpyAsync(bb, boxes.data(), sizeof(Box) * boxes.size(), hipMemcpyHostToDevice, s));
-    region_feat_kernel<<<dim3(n_regions), 256, 0, s>>>((const float*)zb, ld, M, (const float*)ub, n_pc,
-                                                       (const Box*)bb, st.mu32, st.sigma, A->nz, feats);
+    CORR_HIP(hipMemcpyAsync(boxes, hb.data(), box_bytes, hipMemcpyHostToDevice, s));
+    if (n_pairs) CORR_HIP(hipMemcpyAsync(rp, region_pairs, pr_bytes, hipMemcpyHostToDevice, s));
+    const int64_t stride = A->member_stride ? A->member_stride : P;
+    const dim3 g1((unsigned)((P + 255) / 256));
+    if (A->dtype == CORR_F32)
+        self_sim_kernel<float><<<g1, 256, 0, s>>>((const float*)A->data, stride, A->M, A->nx, A->ny, A->nz, D, st.mu32,
+                                                  st.rs32, (float*)simb);
+    else
+        self_sim_kernel<__half><<<g1, 256, 0, s>>>((const __half*)A->data, stride, A->M, A->nx, A->ny, A->nz, D,
+                                                   st.mu32, st.rs32, (float*)simb);
+    hot_spot_kernel<<<dim3(n_regions), 256, 0, s>>>((const float*)simb, boxes, n_hot, r_nms, A->nz, st.mu32, st.sigma,
+                                                    hot, rows);
+    if (n_pairs) {
+        const dim3 g2((unsigned)((n_pairs + 3) / 4));
+        if (A->dtype == CORR_F32)
+            pair_row_kernel<float><<<g2, 256, 0, s>>>((const float*)A->data, stride, A->M, st.mu32, st.rs32, hot, rows,
+                                                      rp, n_pairs, n_hot, x_out);
+        else
+            pair_row_kernel<__half><<<g2, 256, 0, s>>>((const __half*)A->data, stride, A->M, st.mu32, st.rs32, hot,
+                                                       rows, rp, n_pairs, n_hot, x_out);
+    }
     CORR_LAUNCH_CHECK();
+    if (hot_out) CORR_HIP(hipMemcpyAsync(hot_out, hot, hot_bytes, hipMemcpyDeviceToDevice, s));
     CORR_HIP(hipStreamSynchronize(s));
     return CORR_OK;
 }

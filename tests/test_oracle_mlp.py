@@ -77,39 +77,84 @@ def test_silu_derivative():
     np.testing.assert_allclose(R.dsilu(z), (R.silu(z + h) - R.silu(z - h)) / (2 * h), rtol=1e-7, atol=1e-10)
 
 
-def test_region_features_eigenvalues_match_svd():
-    e = synth.make_context(2, 2, (8, 8, 4), M=40, seed=9, n_groups=2, blob_r=2.0, min_region_gap=1)
-    regions = e.regions
-    f, ev = R.region_features(e.data, regions, e.nx, e.ny, e.nz, n_pc=6)
-    x = e.data.astype(np.float64)
-    d = x - x.mean(0)
-    z = d / np.sqrt((d * d).sum(0))
-    s = np.linalg.svd(z, compute_uv=False)
-    np.testing.assert_allclose(ev, (s ** 2 / x.shape[1])[:6], rtol=1e-10)
-    # unit-norm columns: the eigenvalues of G sum to one
-    _, ev_all = R.region_features(e.data, regions[:1], e.nx, e.ny, e.nz, n_pc=40)
-    assert ev_all.sum() == pytest.approx(1.0, abs=1e-12)
-    assert f.shape == (len(regions), 11)
-    assert np.all(f[:, :6] >= 0) and np.all(f[:, :6] <= 1 + 1e-12)
+def _brute_self_similarity(data, nx, ny, nz, D):
+    P = nx * ny * nz
+    out = np.zeros(P)
+    for p in range(P):
+        x, y, z = p % nx, (p // nx) % ny, p // (nx * ny)
+        vals = []
+        for dx, dy, dz in ((D, 0, 0), (-D, 0, 0), (0, D, 0), (0, -D, 0), (0, 0, D), (0, 0, -D)):
+            X, Y, Z = x + dx, y + dy, z + dz
+            if 0 <= X < nx and 0 <= Y < ny and 0 <= Z < nz:
+                q = X + nx * (Y + ny * Z)
+                a, b = data[:, p], data[:, q]
+                if a.std() > 0 and b.std() > 0:
+                    vals.append(np.corrcoef(a, b)[0, 1])
+                else:
+                    vals.append(0.0)
+        out[p] = np.mean(vals) if vals else 0.0
+    return out
 
 
-def test_region_features_rank_one_field():
-    # every point is an affine image of one member vector: G has rank one,
-    # its eigenvector is that vector, and every |projection| is one
-    rng = np.random.default_rng(11)
-    M, nx, ny, nz = 12, 4, 3, 2
+def test_self_similarity_brute_force():
+    rng = np.random.default_rng(21)
+    nx, ny, nz, M = 7, 5, 3, 9
+    data = rng.standard_normal((M, nx * ny * nz))
+    data[:, 4] = 2.5  # a constant point
+    _, _, z = R.standardize(data)
+    for D in (1, 2, 4):
+        np.testing.assert_allclose(R.self_similarity(z, nx, ny, nz, D), _brute_self_similarity(data, nx, ny, nz, D),
+                                   atol=1e-12)
+
+
+def test_self_similarity_rank_one_is_one():
+    rng = np.random.default_rng(2)
+    nx, ny, nz, M = 9, 6, 5, 20
     v = rng.standard_normal(M)
-    a = rng.uniform(0.5, 2.0, nx * ny * nz) * rng.choice([-1, 1], nx * ny * nz)
-    b = rng.standard_normal(nx * ny * nz)
-    data = v[:, None] * a[None, :] + b[None, :]
-    regs = [synth.Region(0, 0, 0, 2, 3, 2), synth.Region(2, 0, 0, 2, 2, 1)]
-    f, ev = R.region_features(data, regs, nx, ny, nz, n_pc=2)
-    assert ev[0] == pytest.approx(1.0, abs=1e-12) and abs(ev[1]) < 1e-12
-    np.testing.assert_allclose(f[:, 0], 1.0, atol=1e-12)
-    # per-point mean of v*a+b is mean(v)*a+b; sigma is |a| * std(v)
-    g0 = regs[0].global_indices(nx, ny)
-    assert f[0, 2] == pytest.approx(np.mean(v.mean() * a[g0] + b[g0]), abs=1e-12)
-    assert f[0, 3] == pytest.approx(np.mean(np.abs(a[g0]) * v.std()), abs=1e-12)
-    # centre of x in [0, 2) on nx = 4 is 0.5 / 4
-    assert f[0, 4] == pytest.approx(0.5 / 4) and f[1, 4] == pytest.approx(2.5 / 4)
-    assert f[0, 5] == pytest.approx(1.0 / 3) and f[1, 6] == pytest.approx(0.0)
+    data = v[:, None] * rng.uniform(0.5, 3.0, nx * ny * nz) + rng.standard_normal(nx * ny * nz)
+    _, _, z = R.standardize(data)
+    np.testing.assert_allclose(R.self_similarity(z, nx, ny, nz, 2), 1.0, atol=1e-12)
+
+
+def test_hot_spots_find_planted_blob_and_suppress():
+    e = synth.make_context(2, 1, (16, 16, 10), M=100, seed=5, n_groups=1, blob_r=3.0, min_region_gap=1)
+    g = e.groups[0]
+    _, _, z = R.standardize(e.data)
+    sim = R.self_similarity(z, e.nx, e.ny, e.nz, 4)
+    for ri, (cx, cy, cz, rad) in zip(g["regions"], g["blobs"]):
+        r = e.regions[ri]
+        h = R.hot_spots(sim, r, e.nx, e.ny, n_hot=4, r_nms=3)
+        x, y, zc = h[0] % e.nx, (h[0] // e.nx) % e.ny, h[0] // (e.nx * e.ny)
+        assert (x - cx) ** 2 + (y - cy) ** 2 + (zc - cz) ** 2 <= (rad + 1) ** 2
+        co = [(p % e.nx, (p // e.nx) % e.ny, p // (e.nx * e.ny)) for p in h]
+        for i in range(4):
+            for j in range(i):
+                assert max(abs(co[i][k] - co[j][k]) for k in range(3)) > 3
+    # a region too small for more than one pick repeats it
+    tiny = synth.Region(0, 0, 0, 2, 2, 2)
+    h = R.hot_spots(sim, tiny, e.nx, e.ny, n_hot=3, r_nms=3)
+    assert h[0] == h[1] == h[2]
+
+
+def test_proposal_inputs_cross_terms_are_pearson():
+    e = synth.make_context(3, 1, (10, 10, 6), M=50, seed=8, n_groups=1, blob_r=2.0, min_region_gap=1)
+    pairs = synth.region_pair_list(len(e.regions))
+    X, hots = R.proposal_inputs(e.data, e.nx, e.ny, e.nz, e.regions, pairs, n_hot=3, D=3, r_nms=2)
+    F = 4 * 3 + 5
+    assert X.shape == (len(pairs), 2 * F + 9)
+    x = e.data.astype(np.float64)
+    for row, (a, b) in zip(X, pairs):
+        c = [abs(np.corrcoef(x[:, hots[a][i]], x[:, hots[b][j]])[0, 1]) for i in range(3) for j in range(3)]
+        np.testing.assert_allclose(row[2 * F:], c, atol=1e-12)
+        ia = e.regions[a].global_indices(e.nx, e.ny)
+        assert row[F - 5] == pytest.approx(x[:, ia].mean(), abs=1e-12)
+        assert row[F - 4] == pytest.approx(x[:, ia].std(0).mean(), abs=1e-12)
+        assert row[F - 3] == pytest.approx((e.regions[a].x0 + 4.5) / e.nx)
+    # pick strengths are the similarity map at the picks; positions are local
+    _, _, z = R.standardize(e.data)
+    sim = R.self_similarity(z, e.nx, e.ny, e.nz, 3)
+    r0 = e.regions[pairs[0][0]]
+    for i in range(3):
+        p = hots[pairs[0][0]][i]
+        assert X[0, 4 * i] == pytest.approx(sim[p], abs=1e-15)
+        assert X[0, 4 * i + 1] == pytest.approx((p % e.nx - r0.x0) / (r0.dx - 1))
