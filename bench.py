@@ -38,6 +38,37 @@ MFMA_F16_PEAK = 2.5e15
 HBM_PEAK = 8.0e12
 
 
+KSG_SOURCE = os.path.join(ROOT, "paper_2309_03308_amd", "csrc", "ksg.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ksg_focus_1e6_pmc.txt")
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per KSG launch from the committed counter summary, or None.
+
+    The summary records FETCH_SIZE and WRITE_SIZE per dispatch of the KSG
+    kernel, the factor that scales them to bytes (from a plain copy of known
+    size in the same runs) and the hash of the kernel source they were taken
+    with; a changed source makes the figures stale and gives None.
+    """
+    try:
+        vals = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get("ksg_source_sha256") != source_hash(KSG_SOURCE):
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -177,8 +208,9 @@ def main():
             "ksg_max": res["ksg"]["value"],
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "ksg_kernel<11,2>",
-                     "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair"},
+                     "traffic": measured_traffic(), "kernel": "ksg_kernel<11>",
+                     "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair, 1e6 pairs per launch",
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
     }
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(e, pairs_np, res, f, ctx, torch, pc)

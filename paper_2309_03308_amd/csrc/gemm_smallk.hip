@@ -58,23 +58,55 @@ __device__ __forceinline__ void sk_load_a(const GemmArgs& g, int64_t row0, int l
         }
 }
 
+// B fragments of K-step s (all parts, WNG column blocks) from LDS.
+template <int PARTS, int WNG, int NS, int BN, int ROWB>
+__device__ __forceinline__ void sk_load_b(const char* smem, int jg, int l32, int half, int s,
+                                          uint4 (&bv)[PARTS][WNG][NS]) {
+#pragma unroll
+    for (int j = 0; j < WNG; ++j) {
+        const char* lb = smem + ((jg + j) * 32 + l32) * ROWB + (2 * s + half) * 16;
+        bv[0][j][s] = *reinterpret_cast<const uint4*>(lb);
+        if constexpr (PARTS == 2) bv[1][j][s] = *reinterpret_cast<const uint4*>(lb + BN * ROWB);
+    }
+}
+
 // One group: WM x WNG blocks of 32x32, the whole K, B blocks jg.. from LDS.
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB>
+// B fragments are read D K-steps ahead of the MFMAs that use them (scheduling
+// fences keep the reads where they are issued), so LDS latency is hidden
+// behind D steps of MFMAs instead of being waited for at every fragment.
+// Lookahead depth: as many K-steps (at most 4) as fit next to the A
+// fragments (doubled when prefetched), the accumulators and ~64 registers of
+// addressing and bookkeeping within 256 VGPRs; 0 when not even one step
+// fits (then each fragment is read just before its MFMAs).
+constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf) {
+    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + wm * wng * 16 + 64;
+    int d = (256 - fixed) / (parts * wng * 4) - 1;
+    if (d > 4) d = 4;
+    if (d > ns) d = ns;
+    return d < 1 ? 0 : d;
+}
+
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
 __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int half,
                                          const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
     using T = SkT<PREC>;
+    constexpr int NS = KV / 2;
+    constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF);
+    uint4 bv[PARTS][WNG][NS];
+#pragma unroll
+    for (int s = 0; s < D; ++s) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s, bv);
+    if constexpr (D > 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WNG; ++j) acc[i][j] = sk_f16{};
 #pragma unroll
-    for (int s = 0; s < KV / 2; ++s) {
+    for (int s = 0; s < NS; ++s) {
+        if (s + D < NS) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s + D, bv);
+        if constexpr (D > 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < WNG; ++j) {
-            const char* lb = smem + ((jg + j) * 32 + l32) * ROWB + (2 * s + half) * 16;
-            const uint4 bh = *reinterpret_cast<const uint4*>(lb);
-            uint4 bl;
-            if constexpr (T::SPLIT) bl = *reinterpret_cast<const uint4*>(lb + BN * ROWB);
+            const uint4 bh = bv[0][j][s];
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
                 if constexpr (T::F32) {
@@ -89,7 +121,7 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8, acc[i][j], 0, 0, 0);
                     if constexpr (T::SPLIT) {
                         const sk_b8 a8l = *reinterpret_cast<const sk_b8*>(&av[PARTS - 1][i][s]);
-                        const sk_b8 b8l = *reinterpret_cast<const sk_b8*>(&bl);
+                        const sk_b8 b8l = *reinterpret_cast<const sk_b8*>(&bv[PARTS - 1][j][s]);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8l, acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8l, b8, acc[i][j], 0, 0, 0);
                     }
@@ -99,7 +131,7 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8, acc[i][j], 0, 0, 0);
                     if constexpr (T::SPLIT) {
                         const sk_h8 a8l = *reinterpret_cast<const sk_h8*>(&av[PARTS - 1][i][s]);
-                        const sk_h8 b8l = *reinterpret_cast<const sk_h8*>(&bl);
+                        const sk_h8 b8l = *reinterpret_cast<const sk_h8*>(&bv[PARTS - 1][j][s]);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8, b8l, acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a8l, b8, acc[i][j], 0, 0, 0);
                     }
@@ -111,7 +143,7 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
 
 // All column groups of the B tile against one A block, folding |r| into the
 // lane's running maximum (strict >: the first occurrence in sweep order).
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB>
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
 __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, int64_t ab, int64_t col0, int l32,
                                          int half, bool self, int32_t nb, const uint4 (&av)[PARTS][WM][KV / 2],
                                          sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
@@ -119,7 +151,7 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
     const bool edge_rows = row0 + 32 * WM > g.na;
 #pragma unroll 1
     for (int jg = 0; jg < BN / 32; jg += WNG) {
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(smem, jg, l32, half, av, acc);
         const int32_t c0 = (int32_t)(col0 + jg * 32);
         const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
         float m = -1.0f;
@@ -202,7 +234,7 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
     if constexpr (!PF) {
         for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
             sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
                                                           lane_ab, lane_jg);
         }
     } else {
@@ -213,12 +245,12 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
         if (ab < ab_end) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
         while (ab < ab_end) {
             if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
                                                           lane_ab, lane_jg);
             ab += 4;
             if (ab >= ab_end) break;
             if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB>(g, smem, ab, col0, l32, half, self, nb, av2, acc, lane_best,
+            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av2, acc, lane_best,
                                                           lane_ab, lane_jg);
             ab += 4;
         }
@@ -237,7 +269,7 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
     const int ab = code / (BN / 32), jg = code - ab * (BN / 32);
     const int64_t row0 = (int64_t)ab * 32 * WM;
     sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
-    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB>(smem, jg, l32, half, av, acc);
+    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(smem, jg, l32, half, av, acc);
     const int32_t c0 = (int32_t)(col0 + jg * 32);
     uint32_t cand = 0xffffffffu, neg = 0;
 #pragma unroll
@@ -354,7 +386,7 @@ bool smallk_config_ok(int prec, int cfg) {
     if (cfg < 0 || cfg >= kNumSkCfgs) return false;
     const SkCfg& c = kSkCfgs[cfg];
     if (prec_split(prec) && c.wm != 1) return false;
-    if (prec == CORR_PREC_F32 && c.wm == 2 && c.pf) return false;  // cfg 6
+    if (prec == CORR_PREC_F32 && c.wm == 2 && (c.pf || c.bn == 256)) return false;  // cfgs 0, 6: register spills
     return true;
 }
 

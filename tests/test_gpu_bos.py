@@ -24,11 +24,13 @@ def _say(msg):
 
 @pytest.fixture(scope="module")
 def env():
+    _say("bos fixture: importing torch")
     import torch
     import __graft_entry__ as g
     g._ensure_built()
     import paper_2309_03308_amd as pc
     e = synth.make_context(4, 2, (12, 12, 6), M=100, seed=21, n_groups=3, blob_r=2.0, min_region_gap=2)
+    _say("bos fixture: creating context")
     ctx = pc.Context(0)
     f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
     regions = [pc.region(*r.as_tuple()) for r in e.regions]
@@ -73,14 +75,16 @@ def _check_history(env, bos, measure, pairs_to_check):
 
 def test_bos_pearson_matches_oracle_replay(env):
     pc, ctx, f = env["pc"], env["ctx"], env["f"]
+    _say(f"  pearson BOS over {len(env['pairs'])} pairs: create")
     bos = pc.Bos(ctx, f, env["regions"], env["pairs"], pc.bos_defaults(seed=3))
     steps = 0
-    while True:
+    for _ in range(64):  # at most 1 + 80 / 8 iterations are ever active
         active = bos.bos_sample_step()
         steps += 1
+        _say(f"  step {steps}: {active} pairs active")
         if active == 0:
             break
-    _say(f"  pearson BOS: {steps} steps")
+    assert active == 0 and steps <= 12
     full, res = _check_history(env, bos, "pearson", range(len(env["pairs"])))
     _say(f"  batches reproduced exactly for {full}/{len(env['pairs'])} pairs")
     assert full >= 0.9 * len(env["pairs"])
