@@ -124,6 +124,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
+    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large"],
+                    help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
+                         "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates")
+    ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
@@ -139,6 +143,115 @@ def main():
     g._ensure_built()
     import paper_2309_03308_amd as pc
 
+    if args.workload == "context":
+        return run_context(args, torch, synth, pc)
+    if args.workload == "large":
+        return run_large(args, torch, synth, pc)
+    return run_focus(args, torch, synth, pc)
+
+
+def _line(args, value, ms, config, **extra):
+    line = {
+        "metric": "point pairs/s for Pearson & KSG-MI at M=100/1000; max-err vs FP64 oracle",
+        "value": value, "unit": "point pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic", "config": config,
+    }
+    line.update(extra)
+    return line
+
+
+def run_context(args, torch, synth, pc):
+    """Context view: batched BOS (20 + 80 samples per pair, uneven batches) over all 3828 region pairs."""
+    e = synth.make_cfg3()
+    ctx = pc.Context(0)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    regions = [pc.region(*r.as_tuple()) for r in e.regions]
+    pairs = synth.region_pair_list(len(e.regions))
+    cfg = pc.bos_defaults(measure=args.measure, k=10, seed=1)
+
+    def view():
+        bos = pc.Bos(ctx, f, regions, pairs, cfg)
+        steps = 0
+        while bos.bos_sample_step() > 0:
+            steps += 1
+        res = bos.bos_results()
+        bos.close()
+        return res, steps
+
+    for _ in range(args.warmup):
+        view()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res, iters = view()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    n_eval = sum(r["n_evaluated"] for r in res)
+    extra = {"breakdown": {"bos_iterations": iters + 1, "evaluations": n_eval,
+                           "context_view_ms": ms, "region_pairs": len(pairs)}}
+    if args.measure == "pearson":
+        truth = np.array([ctx.corr_region_max(f, regions[i], regions[j], "pearson", "f16x3")["value"]
+                          for i, j in pairs])
+        err = truth - np.array([r["value"] for r in res])
+        planted = np.zeros(len(pairs), bool)
+        for gr in e.groups:
+            rs = set(gr["regions"])
+            planted |= np.array([(i in rs and j in rs) for i, j in pairs])
+        extra["bos_error_vs_exhaustive"] = {
+            "mean_abs": float(np.abs(err).mean()), "max_abs": float(np.abs(err).max()),
+            "frac_within_0.01": float(np.mean(np.abs(err) <= 0.01)),
+            "planted_pairs": int(planted.sum()),
+            "planted_mean_abs": float(np.abs(err[planted]).mean()) if planted.any() else None,
+            "normalized_mean": float((err / truth).mean())}
+    line = _line(args, n_eval / (ms / 1e3), ms,
+                 {"workload": f"context view: 352x256x20 ensemble, M=100 FP32, 88 regions of 32x32x20, 3828 "
+                              f"region pairs, batched BOS ({args.measure}, 20 + 80 samples per pair)",
+                  "members": 100, "region_pairs": len(pairs), "measure": args.measure}, **extra)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def run_large(args, torch, synth, pc):
+    """M=1000 FP16 ensemble: 4e6 random pairs (Pearson, KSG) and the focus contraction."""
+    e = synth.make_cfg4()
+    P = e.nx * e.ny * e.nz
+    ctx = pc.Context(0)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    pairs = torch.from_numpy(synth.random_pairs(104, 4_000_000, P)).cuda()
+    ra, rb = [pc.region(*r.as_tuple()) for r in e.regions]
+    out = torch.empty(pairs.shape[0], device="cuda")
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_p = timed(lambda: ctx.corr_pearson_pairs(f, pairs, "f32", out=out), args.steps)
+    t_k = timed(lambda: ctx.corr_ksg_mi_pairs(f, pairs, k=10, out=out), max(1, args.steps // 10))
+    t_g = timed(lambda: ctx.corr_region_max(f, ra, rb, "pearson", args.prec), args.steps)
+    n_focus = 4096 * 4096
+    ms = (t_p + t_k + t_g) * 1e3
+    value = (2 * pairs.shape[0] + n_focus) / (ms / 1e3)
+    line = _line(args, value, ms,
+                 {"workload": "large ensemble: 128x128x32, M=1000 FP16 storage, 4e6 random pairs "
+                              "(Pearson FP32 and KSG k=10) + focus contraction of two 16^3 regions",
+                  "members": 1000, "random_pairs": int(pairs.shape[0]), "focus_pairs": n_focus,
+                  "focus_precision": args.prec},
+                 breakdown={"pearson_pairs_per_s": pairs.shape[0] / t_p, "ksg_pairs_per_s": pairs.shape[0] / t_k,
+                            "focus_pairs_per_s": n_focus / t_g,
+                            "focus_tflops_algorithmic": 2.0 * 1000 * n_focus / t_g / 1e12,
+                            "pearson_hbm_gbps_fp16_operands": pairs.shape[0] * 2 * 1000 * 2 / t_p / 1e9})
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def run_focus(args, torch, synth, pc):
     e = synth.make_cfg2()
     pairs_np = synth.region_pairs_uniform(102, N_KSG, e.regions[0], e.regions[1], e.nx, e.ny)
     ctx = pc.Context(0)
