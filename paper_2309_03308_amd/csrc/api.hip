@@ -186,7 +186,12 @@ static void decode_key(unsigned long long key, const Box& ba, const Box& bb, boo
 
 // Default small-K tile configuration before any tuning: measured fastest on
 // gfx950 for the 20480 x 20480 focus-view shape.
-static int default_smallk_cfg(int prec) { return prec_split(prec) ? 1 : 0; }
+// Untuned defaults: the measured best of the spill-free configurations for
+// each precision class at K = 112 (split modes need one row block per wave).
+static int default_smallk_cfg(int prec) {
+    if (prec_split(prec)) return 4;
+    return prec == CORR_PREC_F32 ? 3 : 2;
+}
 
 static int tuned_smallk_cfg(corr_ctx* ctx, int K, int prec, int64_t na, int64_t nb) {
     for (const corr_tune_rec& r : ctx->tune)
