@@ -186,17 +186,25 @@ static void decode_key(unsigned long long key, const Box& ba, const Box& bb, boo
 
 // Default small-K tile configuration before any tuning: measured fastest on
 // gfx950 for the 20480 x 20480 focus-view shape.
-// Untuned defaults: the measured best of the spill-free configurations for
-// each precision class at K = 112 (split modes need one row block per wave).
-static int default_smallk_cfg(int prec) {
-    if (prec_split(prec)) return 4;
-    return prec == CORR_PREC_F32 ? 3 : 2;
+// Untuned default: the first usable configuration in order of measured
+// preference for the precision class (split modes need one row block per
+// wave; a configuration whose kernel would spill at this K is skipped).
+static int default_smallk_cfg(int prec, int K) {
+    static const int pref16[] = {3, 2, 7, 1, 4, 0, 5, 6};
+    static const int pref32[] = {3, 7, 1, 4, 5, 2, 0};
+    static const int prefsplit[] = {4, 3, 7, 1, 5};
+    const int* p = prec_split(prec) ? prefsplit : (prec == CORR_PREC_F32 ? pref32 : pref16);
+    const int n = prec_split(prec) ? 5 : (prec == CORR_PREC_F32 ? 7 : 8);
+    for (int i = 0; i < n; ++i)
+        if (smallk_config_ok(prec, p[i], K)) return p[i];
+    return 3;
 }
 
 static int tuned_smallk_cfg(corr_ctx* ctx, int K, int prec, int64_t na, int64_t nb) {
     for (const corr_tune_rec& r : ctx->tune)
-        if (r.kind == 0 && r.K == K && r.prec == prec && r.na == na && r.nb == nb) return r.cfg;
-    return default_smallk_cfg(prec);
+        if (r.kind == 0 && r.K == K && r.prec == prec && r.na == na && r.nb == nb && smallk_config_ok(prec, r.cfg, K))
+            return r.cfg;
+    return default_smallk_cfg(prec, K);
 }
 
 static int tuned_ksg_pw(corr_ctx* ctx, int M, int k) {
@@ -227,7 +235,7 @@ static int pearson_exhaustive(corr_ctx* ctx, const corr_field& A, const Box& ba,
     if (small) {
         K = smallk_pad_K(A.M);
         if (cfg < 0) cfg = tuned_smallk_cfg(ctx, (int)K, prec, na, nb);
-        if (!smallk_config_ok(prec, cfg)) return fail(CORR_EINVAL, "tile configuration not valid for this precision");
+        if (!smallk_config_ok(prec, cfg, (int)K)) return fail(CORR_EINVAL, "tile configuration not valid for this precision");
         row_pad = smallk_row_pad(cfg);
         col_pad = smallk_col_pad(cfg);
     } else {
@@ -387,7 +395,7 @@ int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, con
     float best_t = 0.0f;
     std::vector<float> t(reps);
     for (int cfg = 0; cfg < smallk_num_configs(); ++cfg) {
-        if (!smallk_config_ok(prec, cfg)) continue;
+        if (!smallk_config_ok(prec, cfg, smallk_pad_K(A->M))) continue;
         corr_max tmp;
         rc = pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);  // warm-up
         for (int r = 0; r < reps && rc == CORR_OK; ++r) {
@@ -490,7 +498,7 @@ int corr_tune_load(corr_ctx* ctx, const char* path) {
             continue;
         r.na = na;
         r.nb = nb;
-        if (r.kind == 0 && !smallk_config_ok(r.prec, r.cfg)) continue;
+        if (r.kind == 0 && !smallk_config_ok(r.prec, r.cfg, r.K)) continue;
         if (r.kind == 1 && (r.cfg < 1 || r.cfg > 16 || r.K < 2 || ksg_lds_bytes(r.K, r.cfg) > 160 * 1024)) continue;
         if (r.kind != 0 && r.kind != 1) continue;
         tune_store(ctx, r);

@@ -176,7 +176,7 @@ int smallk_num_configs();
 int smallk_row_pad(int cfg);
 int smallk_col_pad(int cfg);
 int smallk_pad_K(int M);
-bool smallk_config_ok(int prec, int cfg);
+bool smallk_config_ok(int prec, int cfg, int K);  // exists for prec and runs without scratch at K
 
 // timing hook helpers (api.hip): bracket a launch with events when enabled
 enum TimedKernel { TK_GEMM = 0, TK_KSG = 1, TK_PAIRS = 2, TK_STD = 3 };

@@ -12,15 +12,19 @@
 //    WM x WNG x K/16 MFMA (32x32x16 f16/bf16, or 32x32x2 f32 with a K
 //    permutation that lets one float4 read feed four steps) into FP32
 //    accumulators, then folds |r| of the group into its running maximum;
-//  - workgroups are (B tile, slice of 4 x apw A blocks); a wave walks every
-//    fourth A block of the slice (optionally prefetching the next fragment
-//    into a second register buffer), so LDS traffic is B only and L2 traffic
-//    is one pass over A per B tile; many small slices keep the tail short.
+//  - the (B tile, A block) work grid is split into one rectangle per XCD
+//    (its A rows fit the XCD's L2) and each rectangle evenly over that XCD's
+//    resident workgroups, in tile-major runs; per run the B tile is staged
+//    once and the waves take every fourth A block (optionally prefetching
+//    the next fragment into a second register buffer), so LDS traffic is B
+//    only, L2 traffic is about one pass over A per B tile, and no workgroup
+//    waits for a second round.
 // Epilogue: each lane keeps its own running max of |r| and the group where
-// it first occurred (no cross-lane work in the sweep); at the end one wave
-// reduction finds the wave maximum, the first group holding it is recomputed
-// from the still-resident B tile, its element with the smallest linear index
-// is located, and one 64-bit atomicMax publishes (|r|, index, sign).
+// it first occurred (no cross-lane work in the sweep); at the end of a run
+// one wave reduction finds the wave maximum, the first group holding it is
+// recomputed from the still-resident B tile, its element with the smallest
+// linear index is located, and one 64-bit atomicMax publishes (|r|, index,
+// sign).
 #include "common.h"
 
 namespace corr {
@@ -79,7 +83,7 @@ __device__ __forceinline__ void sk_load_b(const char* smem, int jg, int l32, int
 // addressing and bookkeeping within 256 VGPRs; 0 when not even one step
 // fits (then each fragment is read just before its MFMAs).
 constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf) {
-    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + wm * wng * 16 + 64;
+    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + wm * wng * 16 + 96;
     int d = (256 - fixed) / (parts * wng * 4) - 1;
     if (d > 4) d = 4;
     if (d > ns) d = ns;
@@ -183,81 +187,14 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
     }
 }
 
-// KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
-template <int PREC, int KV, int WM, int WNG, int BN, int PF>
-__global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_ablk_per_wg, int n_tj) {
-    using T = SkT<PREC>;
-    constexpr int PARTS = T::SPLIT ? 2 : 1;
-    constexpr int ROWB = KV * 16 + 16;  // padded LDS row bytes (conflict-free 16-byte reads)
-    extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int half = lane >> 5, l32 = lane & 31;
-
-    // XCD-grouped order: blocks are dealt round-robin to 8 XCDs; give the
-    // blocks of one XCD consecutive logical ids so they share B tiles.
-    const int G = gridDim.x, b = blockIdx.x;
-    const int lg = (G % 8 == 0) ? ((b % 8) * (G / 8) + b / 8) : b;
-    const int tj = lg % n_tj, slice = lg / n_tj;
-    const int64_t col0 = (int64_t)tj * BN;
-    const int64_t rowb_g = (int64_t)KV * 16;
-
-    // ---- load the B tile (all parts) into LDS once
-    {
-        constexpr int NV = BN * KV;  // 16-byte vectors per part
-#pragma unroll
-        for (int q = 0; q < PARTS; ++q) {
-            const char* src = (const char*)(q ? g.b_lo : g.b_hi) + col0 * rowb_g;
-            char* dst = smem + q * BN * ROWB;
-            for (int v = tid; v < NV; v += 256) {
-                int row = v / KV, c = v - row * KV;
-                *reinterpret_cast<uint4*>(dst + row * ROWB + c * 16) =
-                    *reinterpret_cast<const uint4*>(src + row * rowb_g + c * 16);
-            }
-        }
-    }
-    __syncthreads();
-
-    const int64_t n_ablk = g.na_pad / (32 * WM);
-    const int64_t ab_begin = (int64_t)slice * n_ablk_per_wg;
-    int64_t ab_end = ab_begin + n_ablk_per_wg;
-    if (ab_end > n_ablk) ab_end = n_ablk;
-    const bool self = g.self_col != nullptr;
-    const int32_t nb = (int32_t)g.nb;
-
-    // Per-lane running maximum and the (A block, column group) where it
-    // first occurred; no cross-lane work inside the sweep.
-    float lane_best = -1.0f;
-    int lane_ab = -1, lane_jg = -1;
-
-    uint4 av[PARTS][WM][KV / 2];
-    sk_f16 acc[WM][WNG];
-    if constexpr (!PF) {
-        for (int64_t ab = ab_begin + wave; ab < ab_end; ab += 4) {
-            sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
-                                                          lane_ab, lane_jg);
-        }
-    } else {
-        // A fragments double-buffered in registers: the next block's loads
-        // are in flight while the current block is multiplied
-        uint4 av2[PARTS][WM][KV / 2];
-        int64_t ab = ab_begin + wave;
-        if (ab < ab_end) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
-        while (ab < ab_end) {
-            if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc, lane_best,
-                                                          lane_ab, lane_jg);
-            ab += 4;
-            if (ab >= ab_end) break;
-            if (ab + 4 < ab_end) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
-            sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av2, acc, lane_best,
-                                                          lane_ab, lane_jg);
-            ab += 4;
-        }
-    }
-
-    // ---- one wave reduction; the first group (in sweep order) holding the
-    // wave maximum is recomputed to find its element
+// Wave-level finish of one tile run: one wave reduction, the first group
+// (in sweep order) holding the wave maximum is recomputed from the B tile
+// still in LDS to find its element, and one 64-bit atomicMax publishes
+// (|r|, index, sign).
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
+__device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, int64_t col0, int lane, int l32,
+                                          int half, bool self, int32_t nb, int64_t rowb_g, float lane_best, int lane_ab,
+                                          int lane_jg, uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
     const float wb = sk_wave_max(lane_best);
     if (wb < 0.0f) return;
     int code = (lane_best == wb) ? lane_ab * (BN / 32) + lane_jg : 0x7fffffff;
@@ -299,49 +236,152 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_a
     if (lane == 0 && key) atomicMax(g.key, key);
 }
 
+// Work decomposition. The (B tile, A block) items form a grid of n_tj x
+// n_ablk. Workgroups are dealt round-robin to the 8 XCDs, so workgroup b runs
+// on XCD b % 8: each XCD owns one rectangle of tiles x A blocks (tx_parts x
+// ax_parts rectangles; the A rows of a rectangle fit the XCD's L2), and the
+// workgroups of an XCD split its items evenly in tile-major order. The grid
+// is the number of resident workgroups, so the whole chip works until the
+// end. A workgroup walks its range in runs of one B tile: the tile is staged
+// in LDS once per run and its waves take every fourth A block of the run.
+// KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
+template <int PREC, int KV, int WM, int WNG, int BN, int PF>
+__global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_tj, int tx_parts, int ax_parts) {
+    using T = SkT<PREC>;
+    constexpr int PARTS = T::SPLIT ? 2 : 1;
+    constexpr int ROWB = KV * 16 + 16;  // padded LDS row bytes (conflict-free 16-byte reads)
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int64_t rowb_g = (int64_t)KV * 16;
+    const int64_t n_ablk = g.na_pad / (32 * WM);
+    const bool self = g.self_col != nullptr;
+    const int32_t nb = (int32_t)g.nb;
+
+    const int G = gridDim.x, b = blockIdx.x;
+    const bool xcd = (G % 8 == 0) && tx_parts * ax_parts == 8;
+    const int x = xcd ? (b & 7) : 0;
+    const int64_t r = xcd ? (b >> 3) : b, R = xcd ? (G >> 3) : G;
+    const int txp = xcd ? tx_parts : 1, axp = xcd ? ax_parts : 1;
+    const int tx = x % txp, ax = x / txp;
+    const int64_t t0 = (int64_t)n_tj * tx / txp, t1 = (int64_t)n_tj * (tx + 1) / txp;
+    const int64_t a0 = n_ablk * ax / axp, a1 = n_ablk * (ax + 1) / axp;
+    const int64_t na_x = a1 - a0;
+    const int64_t items = (t1 - t0) * na_x;
+    int64_t it = items * r / R;
+    const int64_t it_end = items * (r + 1) / R;
+
+    uint4 av[PARTS][WM][KV / 2];
+    sk_f16 acc[WM][WNG];
+    while (it < it_end) {
+        const int64_t tj = t0 + it / na_x;
+        const int64_t ab0 = a0 + it % na_x;
+        int64_t run = na_x - it % na_x;
+        if (run > it_end - it) run = it_end - it;
+        const int64_t ab1 = ab0 + run;
+        const int64_t col0 = tj * BN;
+
+        // ---- stage the B tile (all parts); the barrier before protects the
+        // previous run's tile until every wave has finished with it
+        __syncthreads();
+        {
+            constexpr int NV = BN * KV;  // 16-byte vectors per part
+#pragma unroll
+            for (int q = 0; q < PARTS; ++q) {
+                const char* src = (const char*)(q ? g.b_lo : g.b_hi) + col0 * rowb_g;
+                char* dst = smem + q * BN * ROWB;
+                for (int v = tid; v < NV; v += 256) {
+                    int row = v / KV, c = v - row * KV;
+                    *reinterpret_cast<uint4*>(dst + row * ROWB + c * 16) =
+                        *reinterpret_cast<const uint4*>(src + row * rowb_g + c * 16);
+                }
+            }
+        }
+        __syncthreads();
+
+        // Per-lane running maximum and the (A block, column group) where it
+        // first occurred; no cross-lane work inside the sweep.
+        float lane_best = -1.0f;
+        int lane_ab = -1, lane_jg = -1;
+        if constexpr (!PF) {
+            for (int64_t ab = ab0 + wave; ab < ab1; ab += 4) {
+                sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc,
+                                                                 lane_best, lane_ab, lane_jg);
+            }
+        } else {
+            // A fragments double-buffered in registers: the next block's
+            // loads are in flight while the current block is multiplied
+            uint4 av2[PARTS][WM][KV / 2];
+            int64_t ab = ab0 + wave;
+            if (ab < ab1) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
+            while (ab < ab1) {
+                if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc,
+                                                                 lane_best, lane_ab, lane_jg);
+                ab += 4;
+                if (ab >= ab1) break;
+                if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av2, acc,
+                                                                 lane_best, lane_ab, lane_jg);
+                ab += 4;
+            }
+        }
+        sk_finish<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, col0, lane, l32, half, self, nb, rowb_g, lane_best,
+                                                          lane_ab, lane_jg, av, acc);
+        it += run;
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 struct SkCfg {
-    int wm, wng, bn, pf, apw;  // row blocks/wave, column blocks/group, B tile rows, A prefetch, A blocks per wave
+    int wm, wng, bn, pf;  // row blocks per wave, column blocks per group, B tile rows, A prefetch
 };
 
 // Tile configurations the autotuner chooses from (index = config id).
-// apw = 0: long-lived workgroups, about two per CU (each loads its B tile
-// once and sweeps a long slice of A blocks).
 static const SkCfg kSkCfgs[] = {
-    {2, 2, 256, 0, 0}, {1, 4, 256, 0, 0}, {2, 2, 128, 0, 0}, {1, 2, 128, 0, 0},
-    {1, 2, 128, 1, 0}, {1, 4, 256, 1, 0}, {2, 2, 128, 1, 0}, {2, 2, 128, 0, 8},
+    {2, 2, 256, 0}, {1, 4, 256, 0}, {2, 2, 128, 0}, {1, 2, 128, 0},
+    {1, 2, 128, 1}, {1, 4, 256, 1}, {2, 2, 128, 1}, {1, 2, 256, 0},
 };
 constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
 
+// query: report (without launching) whether the instantiation runs without
+// scratch -- a configuration whose registers spill is never used.
 template <int PREC, int KV, int WM, int WNG, int BN, int PF>
-static int launch_sk_t(const GemmArgs& g, int apw, int num_cus, hipStream_t s) {
+static int launch_sk_t(const GemmArgs& g, int num_cus, hipStream_t s, bool query) {
     constexpr int PARTS = SkT<PREC>::SPLIT ? 2 : 1;
     constexpr int ROWB = KV * 16 + 16;
     const size_t lds = (size_t)PARTS * BN * ROWB;
+    const void* fn = (const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF>;
+    if (query) {
+        hipFuncAttributes attr;
+        if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
+            (void)hipGetLastError();
+            return CORR_EUNSUPPORTED;
+        }
+        return attr.localSizeBytes == 0 ? CORR_OK : CORR_EUNSUPPORTED;
+    }
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int nb = 0;
+        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds));
+        per_cu = nb < 1 ? 1 : nb;
+    }
     const int n_tj = (int)(g.nb_pad / BN);
     const int64_t n_ablk = g.na_pad / (32 * WM);
-    // each workgroup: one B tile and a slice of A blocks (4 * apw of them, or
-    // with apw = 0 enough slices for about two workgroups per CU)
-    int64_t per;
-    if (apw > 0) {
-        per = 4 * (int64_t)apw;
-    } else {
-        int64_t want = (int64_t)num_cus * 2;
-        int64_t sl = (want + n_tj - 1) / n_tj;
-        if (sl < 1) sl = 1;
-        if (sl > n_ablk) sl = n_ablk;
-        per = (n_ablk + sl - 1) / sl;
-        per = (per + 3) / 4 * 4;
-    }
-    const int64_t slices = (n_ablk + per - 1) / per;
-    const int64_t grid = slices * n_tj;
-    static bool attr = false;
-    if (!attr) {
-        CORR_HIP(hipFuncSetAttribute((const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
-    gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF><<<dim3((unsigned)grid), 256, lds, s>>>(g, (int)per, n_tj);
+    // XCD rectangles: split A so that each part's rows (all parts of the
+    // split modes) stay within about 2 MiB of the XCD's L2, tiles the rest
+    const int64_t a_bytes = g.na_pad * KV * 16 * PARTS;
+    int ax = 1;
+    while (ax < 8 && a_bytes / ax > (int64_t)2 << 20) ax *= 2;
+    const int tx = 8 / ax;
+    int64_t grid = (int64_t)num_cus * per_cu;
+    grid = (grid + 7) / 8 * 8;
+    const int64_t items = (int64_t)n_tj * n_ablk;
+    if (grid > (items + 7) / 8 * 8) grid = (items + 7) / 8 * 8;
+    if (grid < 8) grid = 8;
+    gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF><<<dim3((unsigned)grid), 256, lds, s>>>(g, n_tj, tx, ax);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -350,29 +390,28 @@ static int launch_sk_t(const GemmArgs& g, int apw, int num_cus, hipStream_t s) {
 int smallk_pad_K(int M) { return M <= 64 ? 64 : (M <= 112 ? 112 : 128); }
 
 template <int PREC, int WM, int WNG, int BN, int PF>
-static int launch_sk_k(const GemmArgs& g, int apw, int num_cus, hipStream_t s) {
+static int launch_sk_k(const GemmArgs& g, int num_cus, hipStream_t s, bool q) {
     constexpr int ES = SkT<PREC>::ES;
     switch (g.K) {
-        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
-        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
-        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN, PF>(g, apw, num_cus, s);
+        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
+        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
+        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
     }
     return fail(CORR_EUNSUPPORTED, "small-K contraction: K must be 64, 112 or 128");
 }
 
 template <int PREC>
-static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s) {
+static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s, bool q) {
     constexpr bool SPLIT = SkT<PREC>::SPLIT;
-    const int apw = kSkCfgs[cfg].apw;
     switch (cfg) {
-        case 0: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 256, 0>(g, apw, nc, s); break;
-        case 1: return launch_sk_k<PREC, 1, 4, 256, 0>(g, apw, nc, s);
-        case 2:
-        case 7: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 128, 0>(g, apw, nc, s); break;
-        case 3: return launch_sk_k<PREC, 1, 2, 128, 0>(g, apw, nc, s);
-        case 4: return launch_sk_k<PREC, 1, 2, 128, 1>(g, apw, nc, s);
-        case 5: return launch_sk_k<PREC, 1, 4, 256, 1>(g, apw, nc, s);
-        case 6: if constexpr (!SPLIT && PREC != CORR_PREC_F32) return launch_sk_k<PREC, 2, 2, 128, 1>(g, apw, nc, s); break;
+        case 0: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 256, 0>(g, nc, s, q); break;
+        case 1: return launch_sk_k<PREC, 1, 4, 256, 0>(g, nc, s, q);
+        case 2: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 2, 128, 0>(g, nc, s, q); break;
+        case 3: return launch_sk_k<PREC, 1, 2, 128, 0>(g, nc, s, q);
+        case 4: return launch_sk_k<PREC, 1, 2, 128, 1>(g, nc, s, q);
+        case 5: return launch_sk_k<PREC, 1, 4, 256, 1>(g, nc, s, q);
+        case 6: if constexpr (!SPLIT && PREC != CORR_PREC_F32) return launch_sk_k<PREC, 2, 2, 128, 1>(g, nc, s, q); break;
+        case 7: return launch_sk_k<PREC, 1, 2, 256, 0>(g, nc, s, q);
     }
     return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
 }
@@ -382,25 +421,46 @@ int smallk_row_pad(int cfg) { return 32 * kSkCfgs[cfg].wm; }
 int smallk_col_pad(int cfg) { return kSkCfgs[cfg].bn; }
 // Register budget: split modes keep hi and lo A fragments (one row block
 // only); FP32 operands with two row blocks cannot also double-buffer A.
-bool smallk_config_ok(int prec, int cfg) {
+static bool smallk_config_static_ok(int prec, int cfg) {
     if (cfg < 0 || cfg >= kNumSkCfgs) return false;
     const SkCfg& c = kSkCfgs[cfg];
     if (prec_split(prec) && c.wm != 1) return false;
-    if (prec == CORR_PREC_F32 && c.wm == 2 && (c.pf || c.bn == 256)) return false;  // cfgs 0, 6: register spills
+    if (prec == CORR_PREC_F32 && c.wm == 2 && c.pf) return false;  // not instantiated
     return true;
+}
+
+static int sk_dispatch(const GemmArgs& g, int cfg, int num_cus, hipStream_t s, bool query) {
+    switch (g.prec) {
+        case CORR_PREC_F32: return launch_sk_p<CORR_PREC_F32>(g, cfg, num_cus, s, query);
+        case CORR_PREC_F16: return launch_sk_p<CORR_PREC_F16>(g, cfg, num_cus, s, query);
+        case CORR_PREC_BF16: return launch_sk_p<CORR_PREC_BF16>(g, cfg, num_cus, s, query);
+        case CORR_PREC_F16X3: return launch_sk_p<CORR_PREC_F16X3>(g, cfg, num_cus, s, query);
+        case CORR_PREC_BF16X3: return launch_sk_p<CORR_PREC_BF16X3>(g, cfg, num_cus, s, query);
+    }
+    return fail(CORR_EUNSUPPORTED, "unknown precision");
+}
+
+// A configuration is usable for (prec, K) when it exists for the precision
+// and its kernel runs without scratch (answer cached per process).
+bool smallk_config_ok(int prec, int cfg, int K) {
+    if (!smallk_config_static_ok(prec, cfg) || prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3) return false;
+    const int ki = K == 64 ? 0 : (K == 112 ? 1 : (K == 128 ? 2 : -1));
+    if (ki < 0) return false;
+    static signed char cache[5][kNumSkCfgs][3] = {};
+    signed char& c = cache[prec][cfg][ki];
+    if (c == 0) {
+        GemmArgs g{};
+        g.prec = prec;
+        g.K = K;
+        c = sk_dispatch(g, cfg, 0, nullptr, true) == CORR_OK ? 1 : -1;
+    }
+    return c > 0;
 }
 
 int launch_gemm_smallk(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {
     if (g.na == 0 || g.nb == 0) return CORR_OK;
-    if (!smallk_config_ok(g.prec, cfg)) return fail(CORR_EINVAL, "small-K contraction: bad tile configuration");
-    switch (g.prec) {
-        case CORR_PREC_F32: return launch_sk_p<CORR_PREC_F32>(g, cfg, num_cus, s);
-        case CORR_PREC_F16: return launch_sk_p<CORR_PREC_F16>(g, cfg, num_cus, s);
-        case CORR_PREC_BF16: return launch_sk_p<CORR_PREC_BF16>(g, cfg, num_cus, s);
-        case CORR_PREC_F16X3: return launch_sk_p<CORR_PREC_F16X3>(g, cfg, num_cus, s);
-        case CORR_PREC_BF16X3: return launch_sk_p<CORR_PREC_BF16X3>(g, cfg, num_cus, s);
-    }
-    return fail(CORR_EUNSUPPORTED, "unknown precision");
+    if (!smallk_config_ok(g.prec, cfg, (int)g.K)) return fail(CORR_EINVAL, "small-K contraction: bad tile configuration");
+    return sk_dispatch(g, cfg, num_cus, s, false);
 }
 
 }  // namespace corr
