@@ -114,7 +114,7 @@ def standardize(data):
     return mu, np.sqrt((d * d).mean(0)), z
 
 
-def self_similarity(z, nx, ny, nz, D=4):
+def self_similarity(z, nx, ny, nz, D=1):
     """s(p) of the module docstring, FP64, shape (P,)."""
     M = z.shape[0]
     zz = z.reshape(M, nz, ny, nx)
@@ -155,7 +155,7 @@ def hot_spots(sim, region, nx, ny, n_hot=4, r_nms=3):
     return picks
 
 
-def proposal_inputs(data, nx, ny, nz, regions, region_pairs, n_hot=4, D=4, r_nms=3):
+def proposal_inputs(data, nx, ny, nz, regions, region_pairs, n_hot=4, D=1, r_nms=3):
     """Pair rows (n_pairs, 2 (4 n_hot + 5) + n_hot^2) and hot spots (n_regions, n_hot)."""
     mu, sig, z = standardize(data)
     sim = self_similarity(z, nx, ny, nz, D)

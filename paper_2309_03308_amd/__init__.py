@@ -317,7 +317,7 @@ class PropMlp:
         return float(loss.value)
 
 
-def corr_proposal_inputs(ctx: Context, A: Field, regions, region_pairs, n_hot: int = 4, D: int = 4, r_nms: int = 3,
+def corr_proposal_inputs(ctx: Context, A: Field, regions, region_pairs, n_hot: int = 4, D: int = 1, r_nms: int = 3,
                          stream=None):
     """Proposal-network inputs (n_pairs, 2 (4 n_hot + 5) + n_hot^2) and the picks (n_regions, n_hot), on the device."""
     import numpy as np

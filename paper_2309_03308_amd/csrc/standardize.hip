@@ -5,7 +5,7 @@
 // stats_kernel: one thread per point, two passes over the members in member
 //   order (mean, then sum of squared deviations). Reads the member-major field
 //   with consecutive threads on consecutive points, so every member row is a
-//   coalesced load.
+//   coalesced load; loads are unrolled eight deep for memory parallelism.
 // transpose_kernel: 64-point x 64-member LDS tile; loads member-major rows
 //   coalesced, normalises, and stores point-major rows (members contiguous),
 //   which is the layout both the pair kernels and the MFMA contraction read.
@@ -21,15 +21,19 @@ template <>
 __device__ __forceinline__ float ld_val<__half>(const __half* p, int64_t i) { return __half2float(p[i]); }
 
 template <typename T, typename ACC>
-__global__ __launch_bounds__(256) void stats_kernel(const T* __restrict__ x, int64_t stride, int M, Box box,
-                                                    Stats st) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void stats_kernel(const T* __restrict__ x, int64_t stride, int M, Box box,
+                                                   Stats st) {
+    int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (i >= box.count()) return;
     int64_t p = box.global(i);
+    // member order is kept in both sums (the unrolled loads are independent,
+    // the additions stay sequential)
     ACC s = 0;
+#pragma unroll 8
     for (int m = 0; m < M; ++m) s += (ACC)ld_val(x, (int64_t)m * stride + p);
     ACC mean = s / (ACC)M;
     ACC q = 0;
+#pragma unroll 8
     for (int m = 0; m < M; ++m) {
         ACC d = (ACC)ld_val(x, (int64_t)m * stride + p) - mean;
         q += d * d;
@@ -108,18 +112,20 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ x,
 int launch_stats(const corr_field& f, const Box& box, bool acc64, Stats st, hipStream_t s) {
     int64_t n = box.count();
     if (n == 0) return CORR_OK;
-    dim3 grid((unsigned)((n + 255) / 256));
+    // one thread per point in 64-thread workgroups: a region of a few
+    // thousand points still spreads over every CU
+    dim3 grid((unsigned)((n + 63) / 64));
     int64_t stride = f.member_stride ? f.member_stride : (int64_t)f.nx * f.ny * f.nz;
     if (f.dtype == CORR_F32) {
         if (acc64)
-            stats_kernel<float, double><<<grid, 256, 0, s>>>((const float*)f.data, stride, f.M, box, st);
+            stats_kernel<float, double><<<grid, 64, 0, s>>>((const float*)f.data, stride, f.M, box, st);
         else
-            stats_kernel<float, float><<<grid, 256, 0, s>>>((const float*)f.data, stride, f.M, box, st);
+            stats_kernel<float, float><<<grid, 64, 0, s>>>((const float*)f.data, stride, f.M, box, st);
     } else {
         if (acc64)
-            stats_kernel<__half, double><<<grid, 256, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
+            stats_kernel<__half, double><<<grid, 64, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
         else
-            stats_kernel<__half, float><<<grid, 256, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
+            stats_kernel<__half, float><<<grid, 64, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
     }
     CORR_LAUNCH_CHECK();
     return CORR_OK;

@@ -1,19 +1,21 @@
 """Learned BOS proposal: training records, training loop and prior cells.
 
-A region pair's inputs (corr_proposal_inputs: self-similarity hot spots of
-both regions and their cross correlations) are mapped by the proposal network
-(PropMlp) to eight outputs:
+A region pair's inputs (corr_proposal_inputs: self-similarity picks of both
+regions, n_hot each, and the |r| between every pick of one region and every
+pick of the other) are mapped by the proposal network (PropMlp) to
+2 + n_hot^2 outputs:
   [0] max |r| over the pair, [1] max MI over the pair,
-  [2:5] location of the maximum in region a, local (x, y, z) / (extent - 1),
-  [5:8] the same in region b.
-The predicted location seeds batched BOS (Sec. 3.1) as its first initial
-sample (bos_set_prior); plain BOS and exhaustive search stay the reference
-for its error. Records come from the method itself: exhaustive region maxima
-(corr_region_max) give the Pearson labels; MI labels are optional (BOS maxima
-when given, else weighted out of the loss).
+  [2 + i n_hot + j] the maximum |r| within Chebyshev radius `radius` of the
+      candidate cell (pick i of region a, pick j of region b).
+The candidate with the largest predicted neighbourhood maximum seeds batched
+BOS (Sec. 3.1) as its first initial sample (bos_set_prior); plain BOS and
+exhaustive search stay the reference for its error. Records come from the
+method itself: exhaustive region maxima (corr_region_max) over the whole pair
+and over each candidate's neighbourhood boxes give the labels; MI labels are
+optional (weighted out of the loss when absent).
 
 Every numeric step runs in the library's kernels; this module only moves
-rows between calls and converts predicted positions into cell indices.
+rows between calls and converts picks into cell indices.
 """
 from __future__ import annotations
 
@@ -21,38 +23,55 @@ import numpy as np
 
 from . import Bos, Context, Field, PropMlp, bos_defaults, corr_proposal_inputs, region
 
-N_OUT = 8
+
+def n_out(n_hot=4):
+    return 2 + n_hot * n_hot
 
 
 def _regs(regions):
-    return [r if not isinstance(r, tuple) else region(*r) for r in regions]
+    return [region(*r) if isinstance(r, tuple) else r for r in regions]
 
 
-def _dims(r):
-    return (r.dx, r.dy, r.dz)
+def _local(p, r, nx, ny):
+    return (p % nx - r.x0, (p // nx) % ny - r.y0, p // (nx * ny) - r.z0)
 
 
-def _local_unit(p, r, nx, ny):
-    x, y, z = p % nx, (p // nx) % ny, p // (nx * ny)
-    return [(v - o) / (d - 1) if d > 1 else 0.0 for v, o, d in ((x, r.x0, r.dx), (y, r.y0, r.dy), (z, r.z0, r.dz))]
+def _nbhd(c, r, radius):
+    """Box of local cells within Chebyshev radius of local cell c, clipped to region r."""
+    lo = [max(0, c[t] - radius) for t in range(3)]
+    hi = [min(d - 1, c[t] + radius) for t, d in enumerate((r.dx, r.dy, r.dz))]
+    return region(r.x0 + lo[0], r.y0 + lo[1], r.z0 + lo[2], hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1)
 
 
-def make_records(ctx: Context, A: Field, regions, region_pairs, mi_values=None, prec="f16x3", n_hot=4, D=4,
-                 r_nms=3):
-    """Inputs (device, n_pairs x width) and labels (device, n_pairs x 8) of a field's region pairs."""
+def inputs(ctx: Context, A: Field, regions, region_pairs, n_hot=4, D=1, r_nms=3):
+    """Network inputs (device) and the picks (host, n_regions x n_hot global indices)."""
+    x, hot = corr_proposal_inputs(ctx, A, _regs(regions), region_pairs, n_hot=n_hot, D=D, r_nms=r_nms)
+    return x, hot.cpu().numpy()
+
+
+def make_records(ctx: Context, A: Field, regions, region_pairs, mi_values=None, prec="f16x3", n_hot=4, D=1, r_nms=3,
+                 radius=2):
+    """Inputs (device, n_pairs x width), labels (device, n_pairs x n_out) and the picks of a field's pairs."""
     torch = __import__("torch")
     regs = _regs(regions)
     rp = np.asarray(region_pairs, np.int32).reshape(-1, 2)
-    x, _ = corr_proposal_inputs(ctx, A, regs, rp, n_hot=n_hot, D=D, r_nms=r_nms)
-    y = np.zeros((rp.shape[0], N_OUT), np.float32)
+    x, hot = inputs(ctx, A, regs, rp, n_hot, D, r_nms)
+    y = np.zeros((rp.shape[0], n_out(n_hot)), np.float32)
     for k, (a, b) in enumerate(rp):
-        m = ctx.corr_region_max(A, regs[a], regs[b], "pearson", prec)
-        y[k, 0] = m["value"]
-        y[k, 2:5] = _local_unit(m["pa"], regs[a], A.nx, A.ny)
-        y[k, 5:8] = _local_unit(m["pb"], regs[b], A.nx, A.ny)
+        ra, rb = regs[a], regs[b]
+        y[k, 0] = ctx.corr_region_max(A, ra, rb, "pearson", prec)["value"]
+        for i in range(n_hot):
+            ba = _nbhd(_local(int(hot[a, i]), ra, A.nx, A.ny), ra, radius)
+            for j in range(n_hot):
+                bb = _nbhd(_local(int(hot[b, j]), rb, A.nx, A.ny), rb, radius)
+                y[k, 2 + i * n_hot + j] = ctx.corr_region_max(A, ba, bb, "pearson", prec)["value"]
     if mi_values is not None:
         y[:, 1] = np.asarray(mi_values, np.float32)
-    return x, torch.from_numpy(y).to(x.device)
+    return x, torch.from_numpy(y).to(x.device), hot
+
+
+def loss_weights(n_hot=4, mi=False):
+    return [1.0, 1.0 if mi else 0.0] + [1.0] * (n_hot * n_hot)
 
 
 def train(net: PropMlp, X, Y, epochs=50, batch=256, lr=1e-3, wd=1e-4, loss_w=None, seed=0):
@@ -73,17 +92,17 @@ def train(net: PropMlp, X, Y, epochs=50, batch=256, lr=1e-3, wd=1e-4, loss_w=Non
     return hist
 
 
-def prior_cells(net: PropMlp, X, regions, region_pairs):
-    """Predicted outputs (host, n_pairs x 8) and BOS prior cells (host, n_pairs x 6)."""
+def prior_cells(net: PropMlp, X, hot, regions, region_pairs, nx, ny, n_hot=4):
+    """Predicted outputs (host) and BOS prior cells (host, n_pairs x 6): the best-scoring candidate of each pair."""
     regs = _regs(regions)
     rp = np.asarray(region_pairs, np.int32).reshape(-1, 2)
     pred = net.forward(X).cpu().numpy()
     cells = np.zeros((rp.shape[0], 6), np.float32)
     for k, (a, b) in enumerate(rp):
-        da, db = _dims(regs[a]), _dims(regs[b])
-        for t in range(3):
-            cells[k, t] = np.clip(pred[k, 2 + t], 0.0, 1.0) * (da[t] - 1)
-            cells[k, 3 + t] = np.clip(pred[k, 5 + t], 0.0, 1.0) * (db[t] - 1)
+        c = int(np.argmax(pred[k, 2:2 + n_hot * n_hot]))
+        i, j = divmod(c, n_hot)
+        cells[k, :3] = _local(int(hot[a, i]), regs[a], nx, ny)
+        cells[k, 3:] = _local(int(hot[b, j]), regs[b], nx, ny)
     return pred, cells
 
 
