@@ -79,22 +79,27 @@ __device__ __forceinline__ void sk_load_b(const char* smem, int jg, int l32, int
 // fences keep the reads where they are issued), so LDS latency is hidden
 // behind D steps of MFMAs instead of being waited for at every fragment.
 // Lookahead depth: as many K-steps (at most 4) as fit next to the A
-// fragments (doubled when prefetched), the accumulators and ~64 registers of
-// addressing and bookkeeping within 256 VGPRs; 0 when not even one step
-// fits (then each fragment is read just before its MFMAs).
+// fragments (doubled when prefetched), both accumulator sets and ~96
+// registers of addressing and bookkeeping within 256 VGPRs; 0 when not even
+// one step fits (then each fragment is read just before its MFMAs).
 constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf) {
-    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + wm * wng * 16 + 96;
+    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + 2 * wm * wng * 16 + 96;
     int d = (256 - fixed) / (parts * wng * 4) - 1;
     if (d > 4) d = 4;
     if (d > ns) d = ns;
     return d < 1 ? 0 : d;
 }
 
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
+// FOLD: while this group's MFMAs run, fold |r| of the previous group's
+// accumulators (prev) into mprev, a slice per K-step, so the VALU work
+// overlaps the matrix pipe instead of following it.
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, bool FOLD = false>
 __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int half,
-                                         const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
+                                         const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG],
+                                         const sk_f16 (&prev)[WM][WNG], float& mprev) {
     using T = SkT<PREC>;
     constexpr int NS = KV / 2;
+    constexpr int NPAIR = WM * WNG * 8;  // element pairs of one group per lane
     constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF);
     uint4 bv[PARTS][WNG][NS];
 #pragma unroll
@@ -142,6 +147,13 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
                 }
             }
         }
+        if constexpr (FOLD) {
+#pragma unroll
+            for (int q = s * NPAIR / NS; q < (s + 1) * NPAIR / NS; ++q) {
+                const int e = 2 * q, i = e / (WNG * 16), j = (e / 16) % WNG, r = e % 16;
+                mprev = fmaxf(mprev, fmaxf(fabsf(prev[i][j][r]), fabsf(prev[i][j][r + 1])));
+            }
+        }
     }
 }
 
@@ -153,9 +165,45 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
                                          sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
     const int64_t row0 = ab * 32 * WM;
     const bool edge_rows = row0 + 32 * WM > g.na;
+    if (!edge_rows && !self && col0 + BN <= nb) {
+        // interior block: accumulators double-buffered, group q-1 folded
+        // while group q is multiplied
+        constexpr int NG = BN / 32 / WNG;
+        sk_f16 acc2[WM][WNG];
+        float unused = 0.0f;
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, 0, l32, half, av, acc, acc, unused);
+#pragma unroll
+        for (int q = 1; q < NG; ++q) {
+            float m = -1.0f;
+            if (q & 1)
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, true>(smem, q * WNG, l32, half, av, acc2, acc, m);
+            else
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, true>(smem, q * WNG, l32, half, av, acc, acc2, m);
+            if (m > lane_best) {
+                lane_best = m;
+                lane_ab = (int)ab;
+                lane_jg = (q - 1) * WNG;
+            }
+        }
+        float m = -1.0f;
+        const sk_f16(&last)[WM][WNG] = ((NG - 1) & 1) ? acc2 : acc;
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WNG; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) m = fmaxf(m, fmaxf(fabsf(last[i][j][r]), fabsf(last[i][j][r + 1])));
+        if (m > lane_best) {
+            lane_best = m;
+            lane_ab = (int)ab;
+            lane_jg = (NG - 1) * WNG;
+        }
+        return;
+    }
+    float unused = 0.0f;
 #pragma unroll 1
     for (int jg = 0; jg < BN / 32; jg += WNG) {
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(smem, jg, l32, half, av, acc);
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, jg, l32, half, av, acc, acc, unused);
         const int32_t c0 = (int32_t)(col0 + jg * 32);
         const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
         float m = -1.0f;
@@ -206,7 +254,8 @@ __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, i
     const int ab = code / (BN / 32), jg = code - ab * (BN / 32);
     const int64_t row0 = (int64_t)ab * 32 * WM;
     sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
-    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(smem, jg, l32, half, av, acc);
+    float unused = 0.0f;
+    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, jg, l32, half, av, acc, acc, unused);
     const int32_t c0 = (int32_t)(col0 + jg * 32);
     uint32_t cand = 0xffffffffu, neg = 0;
 #pragma unroll
