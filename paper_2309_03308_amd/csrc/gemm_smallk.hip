@@ -390,7 +390,7 @@ struct SkCfg {
 // Tile configurations the autotuner chooses from (index = config id).
 static const SkCfg kSkCfgs[] = {
     {2, 2, 256, 0}, {1, 4, 256, 0}, {2, 2, 128, 0}, {1, 2, 128, 0},
-    {1, 2, 128, 1}, {1, 4, 256, 1}, {2, 2, 128, 1}, {1, 2, 256, 0},
+    {1, 2, 128, 1}, {1, 4, 256, 1}, {1, 2, 256, 1}, {1, 2, 256, 0},
 };
 constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
 
@@ -459,7 +459,7 @@ static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s, bool q
         case 3: return launch_sk_k<PREC, 1, 2, 128, 0>(g, nc, s, q);
         case 4: return launch_sk_k<PREC, 1, 2, 128, 1>(g, nc, s, q);
         case 5: return launch_sk_k<PREC, 1, 4, 256, 1>(g, nc, s, q);
-        case 6: if constexpr (!SPLIT && PREC != CORR_PREC_F32) return launch_sk_k<PREC, 2, 2, 128, 1>(g, nc, s, q); break;
+        case 6: return launch_sk_k<PREC, 1, 2, 256, 1>(g, nc, s, q);
         case 7: return launch_sk_k<PREC, 1, 2, 256, 0>(g, nc, s, q);
     }
     return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
@@ -474,7 +474,6 @@ static bool smallk_config_static_ok(int prec, int cfg) {
     if (cfg < 0 || cfg >= kNumSkCfgs) return false;
     const SkCfg& c = kSkCfgs[cfg];
     if (prec_split(prec) && c.wm != 1) return false;
-    if (prec == CORR_PREC_F32 && c.wm == 2 && c.pf) return false;  // not instantiated
     return true;
 }
 

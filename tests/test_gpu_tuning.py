@@ -46,10 +46,9 @@ def test_all_tile_configs_identical(env, tmp_path, prec):
     outs = {}
     for cfg in range(8):
         # configurations with two row blocks per wave are not built for the
-        # split modes, and not with A prefetch for FP32 operands
-        if split and cfg in (0, 2, 6, 7):
-            continue
-        if prec == "f32" and cfg == 6:
+        # split modes (a configuration whose kernel would spill is replaced by
+        # the default when the tuning record is loaded)
+        if split and cfg in (0, 2):
             continue
         _force(ctx, tmp_path, [dict(kind=0, K=112, prec=env["pc"].PREC[prec], na=20480, nb=20480, cfg=cfg, ms=0.0)])
         outs[cfg] = ctx.corr_region_max(f, ra, rb, "pearson", prec)
