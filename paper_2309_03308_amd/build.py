@@ -23,7 +23,8 @@ SOURCES = ["api.hip", "standardize.hip", "pairs.hip", "ksg.hip", "gemm.hip", "ge
 # The contraction kernels only see finite standardised values (|r| <= 1), so
 # they run with IEEE mode off: max/min need no NaN quieting of MFMA results.
 EXTRA = {"gemm.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
-         "gemm_smallk.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
+         "gemm_smallk.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
+         "ksg.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"]}
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
