@@ -8,18 +8,17 @@
 //
 // Design (gfx950, wave64, VALU-bound):
 //  - a wave owns a chunk of PW consecutive pairs and stages, per pair, the
-//    joint samples interleaved as (x_j, y_j) (one ds_read_b128 serves two j)
+//    joint samples as (x_j, y_j), twice in a row (j = 0..M-1, then again),
 //    and both marginals sorted ascending (sorted once per point, not per
 //    pair, by sort_rows_kernel);
 //  - the chunk's PW*M (pair, sample) items are laid densely over the lanes,
-//    so no lane idles when M is not a multiple of 64; the j sweep reads the
-//    item's own pair slot (at most two pairs per 64 items when M >= 64, i.e.
-//    two LDS addresses per read);
-//  - eps_i: the KP1 >= k+1 smallest distances over ALL j (the self distance
-//    0 included) are kept in registers; inserting d is one v_min_f32 and
-//    KP1-1 mutually independent v_med3_f32: t[p] <- med3(t[p-1], d, t[p]).
-//    The (k+1)-th smallest including the zero self distance is exactly the
-//    k-th smallest over j != i, ties kept as a multiset;
+//    so no lane idles when M is not a multiple of 64;
+//  - eps_i: item i reads the M-1 samples that follow it in the doubled row
+//    (i+1 .. i+M-1), so its own zero distance never enters the selection;
+//    the KP >= k smallest distances are kept in registers; inserting d is
+//    one v_min_f32 and KP-1 mutually independent v_med3_f32:
+//    t[p] <- med3(t[p-1], d, t[p]). eps_i = t[k-1] is exactly the k-th
+//    smallest over j != i, ties kept as a multiset;
 //  - n_x,i: since s -> fl32(x_i - s) is monotone, the j with
 //    |fl32(x_i - x_j)| < eps_i form one run of the sorted marginal; two
 //    branch-free binary searches find it (the run includes j = i exactly when
@@ -37,10 +36,10 @@ namespace corr {
 
 constexpr int KSG_WAVES = 4;
 
-template <int KP1>
-__device__ __forceinline__ void topk_insert(float (&t)[KP1], float d) {
+template <int KP>
+__device__ __forceinline__ void topk_insert(float (&t)[KP], float d) {
 #pragma unroll
-    for (int p = KP1 - 1; p >= 1; --p) t[p] = __builtin_amdgcn_fmed3f(t[p - 1], d, t[p]);
+    for (int p = KP - 1; p >= 1; --p) t[p] = __builtin_amdgcn_fmed3f(t[p - 1], d, t[p]);
     t[0] = fminf(t[0], d);
 }
 
@@ -66,7 +65,7 @@ __device__ __forceinline__ void run_counts(const float* sx, const float* sy, int
 }
 
 struct KsgLayout {
-    int mpad2;      // M rounded up to even (interleaved samples, float2 entries)
+    int mdup;       // float2 entries of the doubled sample row (2 M)
     int p2;         // power of two > M (sorted marginals)
     int pw;         // pairs per wave chunk (divides 64)
     int slot_f;     // floats per pair slot
@@ -74,7 +73,7 @@ struct KsgLayout {
     int psi_f;      // floats of the block-shared digamma table
 };
 
-template <int KP1>
+template <int KP>
 __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L) {
     extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -132,15 +131,18 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             if (pi[2] != 1) continue;
             float* slot = wbase + q * L.slot_f;
             float2* xy = reinterpret_cast<float2*>(slot);
-            float* sx = slot + 2 * L.mpad2;
+            float* sx = slot + 2 * L.mdup;
             float* sy = sx + L.p2;
             const int64_t la = pi[0], lb = pi[1];
             const float* xa = a.za + la * a.ld;
             const float* yb = a.zb + lb * a.ld;
             const float* sxa = a.sa + la * L.p2;
             const float* syb = a.sb + lb * L.p2;
-            for (int j = lane; j < L.mpad2; j += 64)
-                xy[j] = (j < M) ? make_float2(xa[j], yb[j]) : make_float2(inf, inf);
+            for (int j = lane; j < M; j += 64) {
+                const float2 v = make_float2(xa[j], yb[j]);
+                xy[j] = v;
+                xy[j + M] = v;
+            }
             for (int j = lane; j < L.p2; j += 64) {
                 sx[j] = sxa[j];
                 sy[j] = syb[j];
@@ -154,29 +156,28 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             const int uc = u < n_items ? u : n_items - 1;
             const int q = uc / M, i = uc - q * M;
             const float* slot = wbase + q * L.slot_f;
-            const float4* xy4 = reinterpret_cast<const float4*>(slot);
-            const float2 me = reinterpret_cast<const float2*>(slot)[i];
-            float tk[KP1];
+            const float2* row = reinterpret_cast<const float2*>(slot);
+            const float2 me = row[i];
+            const float2* nbr = row + i + 1;  // the M-1 other samples, in cyclic order
+            float tk[KP];
 #pragma unroll
-            for (int p = 0; p < KP1; ++p) tk[p] = inf;
-            const int n2 = L.mpad2 / 2;
-            int j2 = 0;
-            for (; j2 + 2 <= n2; j2 += 2) {  // two float4 reads per trip: immediate LDS offsets
-                const float4 v = xy4[j2], w = xy4[j2 + 1];
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - v.z), fabsf(me.y - v.w)));
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - w.x), fabsf(me.y - w.y)));
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - w.z), fabsf(me.y - w.w)));
+            for (int p = 0; p < KP; ++p) tk[p] = inf;
+            int t = 0;
+            for (; t + 4 <= M - 1; t += 4) {  // four reads per trip: immediate LDS offsets
+                const float2 v0 = nbr[t], v1 = nbr[t + 1], v2 = nbr[t + 2], v3 = nbr[t + 3];
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v3.x), fabsf(me.y - v3.y)));
             }
-            if (j2 < n2) {
-                const float4 v = xy4[j2];
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
-                topk_insert<KP1>(tk, fmaxf(fabsf(me.x - v.z), fabsf(me.y - v.w)));
+            for (; t < M - 1; ++t) {
+                const float2 v = nbr[t];
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
             }
             float eps = tk[0];
 #pragma unroll
-            for (int p = 1; p < KP1; ++p) eps = (p == k) ? tk[p] : eps;
-            const float* sx = slot + 2 * L.mpad2;
+            for (int p = 1; p < KP; ++p) eps = (p == k - 1) ? tk[p] : eps;
+            const float* sx = slot + 2 * L.mdup;
             const float* sy = sx + L.p2;
             const int self = eps > 0.0f ? 1 : 0;
             int nx, ny;
@@ -301,10 +302,10 @@ int ksg_default_pw(int M) { return M >= 512 ? 1 : (M >= 192 ? 2 : (M >= 48 ? 4 :
 
 static KsgLayout ksg_layout(int M, int pw) {
     KsgLayout L;
-    L.mpad2 = (M + 1) & ~1;
+    L.mdup = 2 * M;
     L.p2 = ksg_p2(M);
     L.pw = pw > 0 ? pw : ksg_default_pw(M);
-    L.slot_f = 2 * L.mpad2 + 2 * L.p2;
+    L.slot_f = 2 * L.mdup + 2 * L.p2;
     L.slot_f = (L.slot_f + 3) & ~3;
     L.wave_f = L.pw * L.slot_f + L.pw * M + 4 * L.pw;  // + packed counts, pair info
     L.wave_f = (L.wave_f + 3) & ~3;
@@ -317,15 +318,15 @@ size_t ksg_lds_bytes(int M, int pw) {
     return ((size_t)KSG_WAVES * L.wave_f + L.psi_f) * sizeof(float);
 }
 
-template <int KP1>
+template <int KP>
 static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, dim3 grid, size_t lds, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
-        CORR_HIP(hipFuncSetAttribute((const void*)ksg_kernel<KP1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        CORR_HIP(hipFuncSetAttribute((const void*)ksg_kernel<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      160 * 1024));
         attr = true;
     }
-    ksg_kernel<KP1><<<grid, 256, lds, s>>>(a, n_total, L);
+    ksg_kernel<KP><<<grid, 256, lds, s>>>(a, n_total, L);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -341,13 +342,14 @@ int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     int64_t blocks = (n_total + chunk_pairs - 1) / chunk_pairs;
     int64_t cap = (int64_t)num_cus * 8;
     dim3 grid((unsigned)(blocks < cap ? blocks : cap));
-    const int kp1 = a.k + 1;
-    if (kp1 == 11) return launch_kp<11>(a, n_total, L, grid, lds, s);
-    if (kp1 <= 4) return launch_kp<4>(a, n_total, L, grid, lds, s);
-    if (kp1 <= 8) return launch_kp<8>(a, n_total, L, grid, lds, s);
-    if (kp1 <= 12) return launch_kp<12>(a, n_total, L, grid, lds, s);
-    if (kp1 <= 16) return launch_kp<16>(a, n_total, L, grid, lds, s);
-    if (kp1 <= 24) return launch_kp<24>(a, n_total, L, grid, lds, s);
+    // selection width: the smallest instantiated KP >= k
+    const int k = a.k;
+    if (k == 10) return launch_kp<10>(a, n_total, L, grid, lds, s);
+    if (k <= 4) return launch_kp<4>(a, n_total, L, grid, lds, s);
+    if (k <= 8) return launch_kp<8>(a, n_total, L, grid, lds, s);
+    if (k <= 12) return launch_kp<12>(a, n_total, L, grid, lds, s);
+    if (k <= 16) return launch_kp<16>(a, n_total, L, grid, lds, s);
+    if (k <= 24) return launch_kp<24>(a, n_total, L, grid, lds, s);
     return launch_kp<32>(a, n_total, L, grid, lds, s);
 }
 
