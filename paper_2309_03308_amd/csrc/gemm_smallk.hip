@@ -79,11 +79,12 @@ __device__ __forceinline__ void sk_load_b(const char* smem, int jg, int l32, int
 // fences keep the reads where they are issued), so LDS latency is hidden
 // behind D steps of MFMAs instead of being waited for at every fragment.
 // Lookahead depth: as many K-steps (at most 4) as fit next to the A
-// fragments (doubled when prefetched), both accumulator sets and ~96
-// registers of addressing and bookkeeping within 256 VGPRs; 0 when not even
-// one step fits (then each fragment is read just before its MFMAs).
-constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf) {
-    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + 2 * wm * wng * 16 + 96;
+// fragments (doubled when prefetched), both accumulator sets (unless one
+// workgroup per CU leaves them the accumulation registers) and ~96 registers
+// of addressing and bookkeeping within 256 VGPRs; 0 when not even one step
+// fits (then each fragment is read just before its MFMAs).
+constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf, int occ) {
+    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + (occ == 1 ? 0 : 2 * wm * wng * 16) + 96;
     int d = (256 - fixed) / (parts * wng * 4) - 1;
     if (d > 4) d = 4;
     if (d > ns) d = ns;
@@ -93,14 +94,14 @@ constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf) {
 // FOLD: while this group's MFMAs run, fold |r| of the previous group's
 // accumulators (prev) into mprev, a slice per K-step, so the VALU work
 // overlaps the matrix pipe instead of following it.
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, bool FOLD = false>
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC, bool FOLD = false>
 __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int half,
                                          const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG],
                                          const sk_f16 (&prev)[WM][WNG], float& mprev) {
     using T = SkT<PREC>;
     constexpr int NS = KV / 2;
     constexpr int NPAIR = WM * WNG * 8;  // element pairs of one group per lane
-    constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF);
+    constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF, OCC);
     uint4 bv[PARTS][WNG][NS];
 #pragma unroll
     for (int s = 0; s < D; ++s) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s, bv);
@@ -159,7 +160,7 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
 
 // All column groups of the B tile against one A block, folding |r| into the
 // lane's running maximum (strict >: the first occurrence in sweep order).
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC>
 __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, int64_t ab, int64_t col0, int l32,
                                          int half, bool self, int32_t nb, const uint4 (&av)[PARTS][WM][KV / 2],
                                          sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
@@ -171,14 +172,14 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
         constexpr int NG = BN / 32 / WNG;
         sk_f16 acc2[WM][WNG];
         float unused = 0.0f;
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, 0, l32, half, av, acc, acc, unused);
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, 0, l32, half, av, acc, acc, unused);
 #pragma unroll
         for (int q = 1; q < NG; ++q) {
             float m = -1.0f;
             if (q & 1)
-                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, true>(smem, q * WNG, l32, half, av, acc2, acc, m);
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, l32, half, av, acc2, acc, m);
             else
-                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, true>(smem, q * WNG, l32, half, av, acc, acc2, m);
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, l32, half, av, acc, acc2, m);
             if (m > lane_best) {
                 lane_best = m;
                 lane_ab = (int)ab;
@@ -203,7 +204,7 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
     float unused = 0.0f;
 #pragma unroll 1
     for (int jg = 0; jg < BN / 32; jg += WNG) {
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, jg, l32, half, av, acc, acc, unused);
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, l32, half, av, acc, acc, unused);
         const int32_t c0 = (int32_t)(col0 + jg * 32);
         const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
         float m = -1.0f;
@@ -239,7 +240,7 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
 // (in sweep order) holding the wave maximum is recomputed from the B tile
 // still in LDS to find its element, and one 64-bit atomicMax publishes
 // (|r|, index, sign).
-template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF>
+template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC>
 __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, int64_t col0, int lane, int l32,
                                           int half, bool self, int32_t nb, int64_t rowb_g, float lane_best, int lane_ab,
                                           int lane_jg, uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
@@ -255,7 +256,7 @@ __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, i
     const int64_t row0 = (int64_t)ab * 32 * WM;
     sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
     float unused = 0.0f;
-    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, false>(smem, jg, l32, half, av, acc, acc, unused);
+    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, l32, half, av, acc, acc, unused);
     const int32_t c0 = (int32_t)(col0 + jg * 32);
     uint32_t cand = 0xffffffffu, neg = 0;
 #pragma unroll
@@ -294,8 +295,11 @@ __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, i
 // end. A workgroup walks its range in runs of one B tile: the tile is staged
 // in LDS once per run and its waves take every fourth A block of the run.
 // KV = K / 8 (16-bit) or K / 4 (f32): 16-byte vectors per row.
-template <int PREC, int KV, int WM, int WNG, int BN, int PF>
-__global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_tj, int tx_parts, int ax_parts) {
+// OCC = workgroups per CU the register budget is sized for: 2 (two waves
+// per SIMD, 256 registers each) or 1 (one wave per SIMD, whose 512 registers
+// hold the large accumulator tiles).
+template <int PREC, int KV, int WM, int WNG, int BN, int PF, int OCC>
+__global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n_tj, int tx_parts, int ax_parts) {
     using T = SkT<PREC>;
     constexpr int PARTS = T::SPLIT ? 2 : 1;
     constexpr int ROWB = KV * 16 + 16;  // padded LDS row bytes (conflict-free 16-byte reads)
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_t
         if constexpr (!PF) {
             for (int64_t ab = ab0 + wave; ab < ab1; ab += 4) {
                 sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
-                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc,
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av, acc,
                                                                  lane_best, lane_ab, lane_jg);
             }
         } else {
@@ -366,17 +370,17 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_t
             if (ab < ab1) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
             while (ab < ab1) {
                 if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
-                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av, acc,
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av, acc,
                                                                  lane_best, lane_ab, lane_jg);
                 ab += 4;
                 if (ab >= ab1) break;
                 if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
-                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, ab, col0, l32, half, self, nb, av2, acc,
+                sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av2, acc,
                                                                  lane_best, lane_ab, lane_jg);
                 ab += 4;
             }
         }
-        sk_finish<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF>(g, smem, col0, lane, l32, half, self, nb, rowb_g, lane_best,
+        sk_finish<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, col0, lane, l32, half, self, nb, rowb_g, lane_best,
                                                           lane_ab, lane_jg, av, acc);
         it += run;
     }
@@ -384,24 +388,25 @@ __global__ __launch_bounds__(256, 2) void gemm_smallk_kernel(GemmArgs g, int n_t
 
 // ---------------------------------------------------------------- dispatch
 struct SkCfg {
-    int wm, wng, bn, pf;  // row blocks per wave, column blocks per group, B tile rows, A prefetch
+    int wm, wng, bn, pf, occ;  // row blocks per wave, column blocks per group, B tile rows, A prefetch,
+                               // workgroups per CU
 };
 
 // Tile configurations the autotuner chooses from (index = config id).
 static const SkCfg kSkCfgs[] = {
-    {2, 2, 256, 0}, {1, 4, 256, 0}, {2, 2, 128, 0}, {1, 2, 128, 0},
-    {1, 2, 128, 1}, {1, 4, 256, 1}, {1, 2, 256, 1}, {1, 2, 256, 0},
+    {2, 2, 256, 0, 2}, {1, 4, 256, 0, 2}, {2, 2, 128, 0, 2}, {1, 2, 128, 0, 2}, {1, 2, 128, 1, 2},
+    {1, 4, 256, 1, 2}, {1, 2, 256, 1, 2}, {1, 2, 256, 0, 2}, {2, 4, 512, 0, 1}, {4, 2, 512, 0, 1},
 };
 constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
 
 // query: report (without launching) whether the instantiation runs without
 // scratch -- a configuration whose registers spill is never used.
-template <int PREC, int KV, int WM, int WNG, int BN, int PF>
+template <int PREC, int KV, int WM, int WNG, int BN, int PF, int OCC>
 static int launch_sk_t(const GemmArgs& g, int num_cus, hipStream_t s, bool query) {
     constexpr int PARTS = SkT<PREC>::SPLIT ? 2 : 1;
     constexpr int ROWB = KV * 16 + 16;
     const size_t lds = (size_t)PARTS * BN * ROWB;
-    const void* fn = (const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF>;
+    const void* fn = (const void*)gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF, OCC>;
     if (query) {
         hipFuncAttributes attr;
         if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
@@ -430,7 +435,7 @@ static int launch_sk_t(const GemmArgs& g, int num_cus, hipStream_t s, bool query
     const int64_t items = (int64_t)n_tj * n_ablk;
     if (grid > (items + 7) / 8 * 8) grid = (items + 7) / 8 * 8;
     if (grid < 8) grid = 8;
-    gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF><<<dim3((unsigned)grid), 256, lds, s>>>(g, n_tj, tx, ax);
+    gemm_smallk_kernel<PREC, KV, WM, WNG, BN, PF, OCC><<<dim3((unsigned)grid), 256, lds, s>>>(g, n_tj, tx, ax);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -438,13 +443,13 @@ static int launch_sk_t(const GemmArgs& g, int num_cus, hipStream_t s, bool query
 // Small-K contraction K values: members are zero-padded to 64, 112 or 128.
 int smallk_pad_K(int M) { return M <= 64 ? 64 : (M <= 112 ? 112 : 128); }
 
-template <int PREC, int WM, int WNG, int BN, int PF>
+template <int PREC, int WM, int WNG, int BN, int PF, int OCC = 2>
 static int launch_sk_k(const GemmArgs& g, int num_cus, hipStream_t s, bool q) {
     constexpr int ES = SkT<PREC>::ES;
     switch (g.K) {
-        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
-        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
-        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN, PF>(g, num_cus, s, q);
+        case 64: return launch_sk_t<PREC, 64 * ES / 16, WM, WNG, BN, PF, OCC>(g, num_cus, s, q);
+        case 112: return launch_sk_t<PREC, 112 * ES / 16, WM, WNG, BN, PF, OCC>(g, num_cus, s, q);
+        case 128: return launch_sk_t<PREC, 128 * ES / 16, WM, WNG, BN, PF, OCC>(g, num_cus, s, q);
     }
     return fail(CORR_EUNSUPPORTED, "small-K contraction: K must be 64, 112 or 128");
 }
@@ -461,6 +466,8 @@ static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s, bool q
         case 5: return launch_sk_k<PREC, 1, 4, 256, 1>(g, nc, s, q);
         case 6: return launch_sk_k<PREC, 1, 2, 256, 1>(g, nc, s, q);
         case 7: return launch_sk_k<PREC, 1, 2, 256, 0>(g, nc, s, q);
+        case 8: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 4, 512, 0, 1>(g, nc, s, q); break;
+        case 9: if constexpr (!SPLIT) return launch_sk_k<PREC, 4, 2, 512, 0, 1>(g, nc, s, q); break;
     }
     return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
 }
@@ -492,6 +499,8 @@ static int sk_dispatch(const GemmArgs& g, int cfg, int num_cus, hipStream_t s, b
 // and its kernel runs without scratch (answer cached per process).
 bool smallk_config_ok(int prec, int cfg, int K) {
     if (!smallk_config_static_ok(prec, cfg) || prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3) return false;
+    const int es = prec == CORR_PREC_F32 ? 4 : 2, parts = prec_split(prec) ? 2 : 1;
+    if ((size_t)parts * kSkCfgs[cfg].bn * (K * es + 16) > 160 * 1024) return false;  // B tile must fit LDS
     const int ki = K == 64 ? 0 : (K == 112 ? 1 : (K == 128 ? 2 : -1));
     if (ki < 0) return false;
     static signed char cache[5][kNumSkCfgs][3] = {};
