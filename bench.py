@@ -124,9 +124,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
-    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large"],
+    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall"],
                     help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
-                         "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates")
+                         "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates; onetoall: one "
+                         "reference point against every point of a 250x352x20 field (M=100) and of the "
+                         "128x128x32 field (M=1000)")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -147,6 +149,8 @@ def main():
         return run_context(args, torch, synth, pc)
     if args.workload == "large":
         return run_large(args, torch, synth, pc)
+    if args.workload == "onetoall":
+        return run_onetoall(args, torch, synth, pc)
     return run_focus(args, torch, synth, pc)
 
 
@@ -249,6 +253,46 @@ def run_large(args, torch, synth, pc):
                             "pearson_hbm_gbps_fp16_operands": pairs.shape[0] * 2 * 1000 * 2 / t_p / 1e9})
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+def run_onetoall(args, torch, synth, pc):
+    """One reference point against every grid point (the shape of the paper's performance table)."""
+    out = {}
+    for label, make, M in (("M100", lambda: synth.make_field("onetoall-250x352x20-M100", 5, 100, 250, 352, 20, [], []),
+                            100),
+                           ("M1000", synth.make_cfg4, 1000)):
+        e = make()
+        P = e.nx * e.ny * e.nz
+        f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+        ctx = pc.Context(0)
+        ref = (e.nx // 2) + e.nx * ((e.ny // 2) + e.ny * (e.nz // 2))
+        pairs = torch.stack([torch.full((P,), ref, dtype=torch.int32), torch.arange(P, dtype=torch.int32)], 1).cuda()
+        res = torch.empty(P, device="cuda")
+
+        def timed(fn, reps):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        tp = timed(lambda: ctx.corr_pearson_pairs(f, pairs, "f32", out=res), args.steps)
+        tk = timed(lambda: ctx.corr_ksg_mi_pairs(f, pairs, k=10, out=res), max(1, args.steps // 5))
+        out[label] = {"points": P, "pearson_s": tp, "ksg_s": tk, "pearson_pairs_per_s": P / tp,
+                      "ksg_pairs_per_s": P / tk}
+        ctx.close()
+        del f, pairs, res
+        torch.cuda.empty_cache()
+    ms = (out["M100"]["pearson_s"] + out["M100"]["ksg_s"]) * 1e3
+    line = _line(args, 2 * out["M100"]["points"] / (ms / 1e3), ms,
+                 {"workload": "one-to-all: one reference point against all 1.76e6 points of a 250x352x20 ensemble "
+                              "(M=100, FP32), Pearson and KSG k=10; also the 524288-point M=1000 FP16 field",
+                  "members": 100, "points": out["M100"]["points"]},
+                 breakdown=out)
+    print(json.dumps(line), flush=True)
 
 
 def run_focus(args, torch, synth, pc):

@@ -190,7 +190,7 @@ static void decode_key(unsigned long long key, const Box& ba, const Box& bb, boo
 // preference for the precision class (split modes need one row block per
 // wave; a configuration whose kernel would spill at this K is skipped).
 static int default_smallk_cfg(int prec, int K) {
-    static const int pref16[] = {7, 6, 5, 3, 2, 1, 4, 0};
+    static const int pref16[] = {6, 7, 5, 3, 2, 1, 4, 0};
     static const int pref32[] = {7, 6, 3, 1, 4, 5, 2, 0};
     static const int prefsplit[] = {3, 4, 6, 7, 1, 5};
     const int* p = prec_split(prec) ? prefsplit : (prec == CORR_PREC_F32 ? pref32 : pref16);
