@@ -51,7 +51,7 @@ typedef struct bos_config {
     int32_t n_init;     /* initial design per pair, >= 2 */
     int32_t n_total;    /* samples per pair, <= 128; n_total - n_init a positive multiple of 8 */
     int32_t n_uniform;  /* uniform candidates per iteration */
-    int32_t n_local;    /* local candidates per iteration; n_uniform + n_local in [1, 1024] */
+    int32_t n_local;    /* local candidates per iteration; n_uniform + n_local in [64, 1024] */
     double kappa;       /* UCB weight (0.5) */
     double lengthscale; /* Matern length scale in cells (3) */
     double local_sd;    /* sd of the local candidates in cells (1) */
@@ -77,12 +77,14 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
                bos_state** out, corr_stream_t stream);
 
 /*
- * Proposal prior (the learned proposal): HOST float [n_pairs][6] predicted
- * argmax cell (local coordinates of the A cell, then the B cell) per pair,
- * or a negative first coordinate for none. The cell rounded to the box
- * replaces the first cell of the initial design, and the local candidates
- * are drawn around it until an observation beats the prior cell's value.
- * Must be called before the first bos_sample_step.
+ * Proposal prior (the learned proposal): HOST float [n_pairs][6] proposed
+ * cell (local coordinates of the A cell, then the B cell) per pair, or a
+ * negative first coordinate for none. The cell, rounded and clamped to the
+ * box, replaces the first cell of the initial design; like every
+ * observation it then steers the GP, and the local candidates are drawn
+ * around the incumbent (the best observation so far), which it is as long
+ * as nothing better has been seen. Must be called before the first
+ * bos_sample_step (CORR_ESTATE otherwise).
  */
 int bos_set_prior(bos_state* st, const float* cells);
 
