@@ -14,6 +14,7 @@ from .fields import (  # noqa: F401
     make_cfg3,
     make_cfg4,
     make_context,
+    make_two_variables,
     context_regions,
     region_pair_list,
     make_field,

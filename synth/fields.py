@@ -245,6 +245,28 @@ def make_cfg3(M: int = 100, seed: int = 3) -> Ensemble:
     return make_context(11, 8, (32, 32, 20), M, seed, 8, 4.0, 3, f"context-352x256x20-M{M}")
 
 
+def make_two_variables(nx=24, ny=16, nz=8, M=100, seed=7, rho=0.8, blob_r=2.5):
+    """Two variables U, V of one ensemble on the same grid (independent
+    smoothed noise), with one shared member signal planted in a blob of U in
+    the left half and a blob of V in the right half, so that U there and V
+    there correlate with rho. Returns (U, V, regions) with regions the left
+    and right halves."""
+    rng = np.random.Generator(np.random.PCG64(20_000 + seed))
+    fu = smooth_noise(rng, M, nz, ny, nx)
+    fv = smooth_noise(rng, M, nz, ny, nx)
+    s = rng.standard_normal(M).astype(np.float32)
+    a = math.sqrt(rho / (1.0 - rho))
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for f, cx in ((fu, nx // 4), (fv, 3 * nx // 4)):
+        mask = (xx - cx) ** 2 + (yy - ny // 2) ** 2 + (zz - nz // 2) ** 2 <= blob_r * blob_r
+        f[:, mask] = ((f[:, mask] + np.float32(a) * s[:, None]) / np.float32(math.sqrt(1.0 + a * a))).astype(
+            np.float32)
+    regs = [Region(0, 0, 0, nx // 2, ny, nz), Region(nx // 2, 0, 0, nx - nx // 2, ny, nz)]
+    U = Ensemble("U", np.ascontiguousarray(fu.reshape(M, -1)), nx, ny, nz, regs, [], seed)
+    V = Ensemble("V", np.ascontiguousarray(fv.reshape(M, -1)), nx, ny, nz, regs, [], seed)
+    return U, V, regs
+
+
 def region_pair_list(n_regions: int) -> np.ndarray:
     """All unordered pairs (i < j) of regions, int32 (n, 2)."""
     i, j = np.triu_indices(n_regions, 1)

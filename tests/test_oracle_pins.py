@@ -230,3 +230,28 @@ def test_matmul_region_max_agrees_with_brute_force():
     assert a["value"] < 1.0 and b["value"] == pytest.approx(a["value"], abs=1e-13)
     assert (b["la"], b["lb"]) == (a["la"], a["lb"])
     assert a["n_evaluated"] == b["n_evaluated"] == ia.size * (ia.size - 1)
+
+
+# ------------------------------------------------------------ two variables
+def test_two_field_paths_match_one_field_construction():
+    """Pairs across two fields equal the same pairs inside one field that holds
+    both rows (statistics are per point, so the data_b plumbing must give the
+    identical result)."""
+    import synth as _s
+    U, V, regs = _s.make_two_variables(nx=12, ny=8, nz=4, M=40, seed=3)
+    rng = np.random.default_rng(4)
+    P = U.nx * U.ny * U.nz
+    pa = rng.integers(0, P, 64)
+    pb = rng.integers(0, P, 64)
+    pairs = np.stack([pa, pb], 1).astype(np.int32)
+    r2 = oracle.pearson_pairs(U.data, pairs, data_b=V.data)
+    mi2, c2 = oracle.ksg_pairs(U.data, pairs, 5, data_b=V.data)
+    for t, (a, b) in enumerate(pairs):
+        W = U.data.copy()
+        W[:, (a + 1) % P] = V.data[:, b]  # V's row placed next to a in one field
+        one = np.array([[a, (a + 1) % P]], np.int32)
+        assert oracle.pearson_pairs(W, one)[0] == r2[t]
+        mi1, c1 = oracle.ksg_pairs(W, one, 5)
+        assert mi1[0] == mi2[t] and np.array_equal(c1[0], c2[t])
+        x, y = U.data[:, a].astype(np.float64), V.data[:, b].astype(np.float64)
+        assert r2[t] == pytest.approx(np.corrcoef(x, y)[0, 1], abs=1e-12)
