@@ -124,11 +124,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
-    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall"],
+    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree"],
                     help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
                          "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates; onetoall: one "
                          "reference point against every point of a 250x352x20 field (M=100) and of the "
-                         "128x128x32 field (M=1000)")
+                         "128x128x32 field (M=1000); meantree: mean-tree levels f=2,4 of a 180-member "
+                         "640x704x64 field, and brick maxima on the levels of the 352x256x20 field")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -151,6 +152,8 @@ def main():
         return run_large(args, torch, synth, pc)
     if args.workload == "onetoall":
         return run_onetoall(args, torch, synth, pc)
+    if args.workload == "meantree":
+        return run_meantree(args, torch, synth, pc)
     return run_focus(args, torch, synth, pc)
 
 
@@ -292,6 +295,88 @@ def run_onetoall(args, torch, synth, pc):
                               "(M=100, FP32), Pearson and KSG k=10; also the 524288-point M=1000 FP16 field",
                   "members": 100, "points": out["M100"]["points"]},
                  breakdown=out)
+    print(json.dumps(line), flush=True)
+
+
+def run_meantree(args, torch, synth, pc):
+    """Mean-tree levels (HBM-bound) and the deviation of brick maxima estimated on them."""
+    M, nx, ny, nz = 180, 640, 704, 64
+    print(f"meantree: generating {M} x {nx}x{ny}x{nz} on the device", file=sys.stderr, flush=True)
+    X = synth.smooth_field_torch(M, nx, ny, nz, seed=11)
+    A = pc.Field(X, nx, ny, nz)
+    ctx = pc.Context(0)
+    P = nx * ny * nz
+    outs, nbytes = {}, {}
+    for fct in (2, 4):
+        NX, NY, NZ = pc.level_dims(nx, ny, nz, fct)
+        outs[fct] = torch.empty((M, NX * NY * NZ), device="cuda")
+        nbytes[fct] = 4.0 * M * (P + NX * NY * NZ)  # read every value once, write every mean once
+
+    def step():
+        for fct in (2, 4):
+            ctx.corr_block_means(A, fct, "f32", out=outs[fct])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.set_timing(True)
+    kern = {}
+    for fct in (2, 4):
+        t = []
+        for _ in range(args.steps):
+            ctx.corr_block_means(A, fct, "f32", out=outs[fct])
+            t.append(ctx.kernel_time_ms("block_means"))
+        kern[fct] = float(np.mean(t))
+    ctx.set_timing(False)
+    del X, A, outs
+    torch.cuda.empty_cache()
+
+    # brick maxima at f = 1, 2, 4 over every pair of the 88 bricks (32x32x20) of
+    # the 352x256x20 context field (exhaustive Pearson, the quantity BOS estimates)
+    print("meantree: brick maxima on the levels", file=sys.stderr, flush=True)
+    e = synth.make_cfg3()
+    F1 = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    regs = [pc.region(*r.as_tuple()) for r in e.regions]
+    pairs = synth.region_pair_list(len(regs))
+    maxima, tmax = {}, {}
+    for fct in (1, 2, 4):
+        Fl = F1 if fct == 1 else ctx.corr_block_means(F1, fct, "f32")
+        lr = [pc.region_at_level(r, fct) for r in regs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        maxima[fct] = np.array([ctx.corr_region_max(Fl, lr[a], lr[b], "pearson", "f16x3")["value"] for a, b in pairs])
+        tmax[fct] = time.perf_counter() - t0
+    dev = {}
+    for fct in (2, 4):
+        d = maxima[fct] - maxima[1]
+        dev[f"f{fct}"] = {"mean_rel_dev": float(np.mean(np.abs(d) / maxima[1])), "mean_abs_dev": float(np.mean(np.abs(d))),
+                          "mean_signed_dev": float(np.mean(d)), "s_all_pairs": tmax[fct]}
+    ctx.close()
+
+    tot_bytes = nbytes[2] + nbytes[4]
+    achieved = nbytes[2] / (kern[2] / 1e3) / 1e9
+    line = {
+        "metric": "HBM bytes/s building mean-tree levels f=2,4 (read the field, write the block means)",
+        "value": tot_bytes / (ms / 1e3), "unit": "B/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (device-generated smoothed Gaussian noise)",
+        "config": {"workload": "mean-tree levels f=2 and f=4 of a 180-member 640x704x64 FP32 ensemble "
+                               "(20.8 GB, each level from the initial data); brick maxima at f=1,2,4 for the "
+                               "3828 pairs of 32x32x20 bricks of the 352x256x20 M=100 field",
+                   "members": M, "points": P},
+        "breakdown": {"kernel_ms": {f"f{k}": v for k, v in kern.items()},
+                      "kernel_GBps": {f"f{k}": nbytes[k] / (kern[k] / 1e3) / 1e9 for k in kern},
+                      "deviation_of_maxima": dev, "mean_max_f1": float(np.mean(maxima[1])),
+                      "s_all_pairs_f1": tmax[1]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "traffic": None, "kernel": "block_means_kernel<float, float, 2>",
+                     "work": "4 B read per input value + 4 B written per block mean, 180 x 28.8e6 values per launch"},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -198,12 +198,33 @@ int corr_tune_save(corr_ctx* ctx, const char* path);
 int corr_tune_load(corr_ctx* ctx, const char* path);
 
 /*
+ * One level of the mean tree (Sec. 4, sampling from spatial aggregates):
+ * for every member m and every block of f x f x f grid points, the mean of
+ * A's values over the block. Blocks tile the grid from the origin; a block on
+ * a high face holds the min(f, n - f*X) points left on that axis and its
+ * mean is over those. The result is an ensemble field of the same M on a
+ * ceil(nx/f) x ceil(ny/f) x ceil(nz/f) grid (x fastest), on which every
+ * other call of this library can estimate brick-pair maxima (Sec. 5 compares
+ * maxima at f = 1, 2 and 4).
+ *   f:          a power of two in [1, 64] (else CORR_EINVAL).
+ *   out:        device, member-major: value(m, q) = out[m * out_stride + q];
+ *               caller-owned, must not overlap A's data.
+ *   out_dtype:  CORR_F32 or CORR_F16 (else CORR_EUNSUPPORTED).
+ *   out_stride: elements between members; 0 = the level's point count
+ *               (smaller non-zero values are CORR_EINVAL).
+ * Sums in FP64; the mean is rounded once to out_dtype.
+ */
+int corr_block_means(corr_ctx* ctx, const corr_field* A, int f, int out_dtype, void* out, int64_t out_stride,
+                     corr_stream_t stream);
+
+/*
  * Kernel timing hook (instrumentation, no effect on results). With timing
  * on, the main kernel of each call is bracketed by HIP events recorded on the
  * call's stream. corr_kernel_time_ms waits for the last such kernel of class
  * `which` and returns its duration in milliseconds (-1 if none yet).
  * which: 0 = Pearson contraction (exhaustive region max), 1 = KSG,
- *        2 = Pearson pair list, 3 = standardisation (statistics + layout).
+ *        2 = Pearson pair list, 3 = standardisation (statistics + layout),
+ *        4 = mean-tree level (corr_block_means).
  */
 int corr_set_timing(corr_ctx* ctx, int on);
 int corr_kernel_time_ms(corr_ctx* ctx, int which, float* ms);

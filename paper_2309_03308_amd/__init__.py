@@ -84,7 +84,7 @@ class Context:
             pass
 
     # ------------------------------------------------------------------ timing
-    KERNEL_CLASSES = {"gemm": 0, "ksg": 1, "pairs": 2, "standardize": 3}
+    KERNEL_CLASSES = {"gemm": 0, "ksg": 1, "pairs": 2, "standardize": 3, "block_means": 4}
 
     def set_timing(self, on: bool = True):
         _lib.check(self.L.corr_set_timing(self.h, 1 if on else 0))
@@ -165,6 +165,40 @@ class Context:
                                           ctypes.byref(out), _stream_ptr(stream)))
         return dict(value=out.value, signed_value=out.signed_value, pa=out.pa, pb=out.pb,
                     n_evaluated=out.n_evaluated)
+
+    # ------------------------------------------------------------------ mean tree
+    def corr_block_means(self, A: Field, f: int, dtype="f32", out=None, stream=None) -> Field:
+        """One mean-tree level: the field of f^3 block means (a new Field, or one over `out`)."""
+        torch = _torch()
+        if int(f) < 1:  # the library reports the bad factor before anything is sized
+            _lib.check(self.L.corr_block_means(self.h, ctypes.byref(A.c), int(f), 0, None, 0, _stream_ptr(stream)))
+        NX, NY, NZ = level_dims(A.nx, A.ny, A.nz, f)
+        tdt = {"f32": torch.float32, "f16": torch.float16}[dtype]
+        if out is None:
+            out = torch.empty((A.M, NX * NY * NZ), dtype=tdt, device=A.data.device)
+        elif out.dtype != tdt or out.dim() != 2 or out.shape[0] != A.M or out.shape[1] < NX * NY * NZ \
+                or out.stride(1) != 1:
+            raise ValueError("out must be a (M, >= level points) tensor of the requested dtype")
+        _lib.check(self.L.corr_block_means(self.h, ctypes.byref(A.c), int(f),
+                                           _lib.CORR_F32 if dtype == "f32" else _lib.CORR_F16,
+                                           ctypes.c_void_p(out.data_ptr()), int(out.stride(0)), _stream_ptr(stream)))
+        return Field(out, NX, NY, NZ)
+
+    def mean_tree(self, A: Field, factors=(2, 4), dtype="f32", stream=None) -> dict:
+        """Levels of the mean tree, each computed from the initial data: {f: Field}."""
+        return {int(f): self.corr_block_means(A, f, dtype, stream=stream) for f in factors}
+
+
+def level_dims(nx, ny, nz, f):
+    """Grid extent of the mean-tree level with factor f."""
+    return ((nx + f - 1) // f, (ny + f - 1) // f, (nz + f - 1) // f)
+
+
+def region_at_level(r: corr_region, f: int) -> corr_region:
+    """The level-f blocks that cover a brick (exact for bricks aligned to f)."""
+    x1, y1, z1 = r.x0 + r.dx, r.y0 + r.dy, r.z0 + r.dz
+    x0, y0, z0 = r.x0 // f, r.y0 // f, r.z0 // f
+    return corr_region(x0, y0, z0, (x1 + f - 1) // f - x0, (y1 + f - 1) // f - y0, (z1 + f - 1) // f - z0)
 
 
 def bos_defaults(**overrides) -> bos_config:

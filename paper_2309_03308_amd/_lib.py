@@ -84,6 +84,7 @@ SIGNATURES = {
     "bos_load": (_I, [_P, ctypes.c_char_p, _P]),
     "bos_destroy": (None, [_P]),
     "corr_kernel_time_ms": (_I, [_P, _I, ctypes.POINTER(ctypes.c_float)]),
+    "corr_block_means": (_I, [_P, ctypes.POINTER(corr_field), _I, _I, _P, _I64, _P]),
     "prop_mlp_create": (_I, [_P, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "prop_mlp_num_params": (_I, [_P, ctypes.POINTER(_I64)]),
     "prop_mlp_get_params": (_I, [_P, _P]),

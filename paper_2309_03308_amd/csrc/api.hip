@@ -326,7 +326,7 @@ int corr_create(int device, corr_ctx** out) {
     delete[] h;
     if (e == hipSuccess) e = hipMalloc(&c->keys, 64 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc(&c->keys_host, 64 * sizeof(unsigned long long), hipHostMallocDefault);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    for (int i = 0; i < TK_COUNT && e == hipSuccess; ++i) {
         e = hipEventCreate(&c->ev_start[i]);
         if (e == hipSuccess) e = hipEventCreate(&c->ev_stop[i]);
     }
@@ -347,7 +347,7 @@ void corr_destroy(corr_ctx* c) {
     if (c->psi) (void)hipFree(c->psi);
     if (c->keys) (void)hipFree(c->keys);
     if (c->keys_host) (void)hipHostFree(c->keys_host);
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TK_COUNT; ++i) {
         if (c->ev_start[i]) (void)hipEventDestroy(c->ev_start[i]);
         if (c->ev_stop[i]) (void)hipEventDestroy(c->ev_stop[i]);
     }
@@ -362,7 +362,7 @@ int corr_set_timing(corr_ctx* ctx, int on) {
 
 int corr_kernel_time_ms(corr_ctx* ctx, int which, float* ms) {
     if (!ctx || !ms) return fail(CORR_EINVAL, "null argument");
-    if (which < 0 || which > 3) return fail(CORR_EINVAL, "unknown kernel class");
+    if (which < 0 || which >= TK_COUNT) return fail(CORR_EINVAL, "unknown kernel class");
     *ms = -1.0f;
     if (!ctx->ev_valid[which]) return CORR_OK;
     CORR_HIP(hipEventSynchronize(ctx->ev_stop[which]));
@@ -727,6 +727,23 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     decode_key(k0, ba, bb, false, out);
     out->n_evaluated = (int64_t)k1;
     return CORR_OK;
+}
+
+int corr_block_means(corr_ctx* ctx, const corr_field* A, int f, int out_dtype, void* out, int64_t out_stride,
+                     corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if (f < 1 || f > 64 || (f & (f - 1)) != 0) return fail(CORR_EINVAL, "f must be a power of two in [1, 64]");
+    if (out_dtype != CORR_F32 && out_dtype != CORR_F16) return fail(CORR_EUNSUPPORTED, "unsupported output dtype");
+    if (!out) return fail(CORR_EINVAL, "null output");
+    const int64_t nout = (int64_t)((A->nx + f - 1) / f) * ((A->ny + f - 1) / f) * ((A->nz + f - 1) / f);
+    if (out_stride != 0 && out_stride < nout) return fail(CORR_EINVAL, "out_stride smaller than the level's grid");
+    hipStream_t s = (hipStream_t)stream;
+    timing_begin(ctx, TK_AGG, s);
+    rc = launch_block_means(*A, f, out_dtype, out, out_stride, s);
+    timing_end(ctx, TK_AGG, s);
+    return rc;
 }
 
 }  // extern "C"

@@ -83,9 +83,9 @@ struct corr_ctx {
     unsigned long long* keys_host = nullptr;  // pinned host mirror
     // kernel timing hook: events per kernel class (see corr_set_timing)
     bool timing = false;
-    hipEvent_t ev_start[4] = {};
-    hipEvent_t ev_stop[4] = {};
-    bool ev_valid[4] = {};
+    hipEvent_t ev_start[5] = {};
+    hipEvent_t ev_stop[5] = {};
+    bool ev_valid[5] = {};
 };
 
 namespace corr {
@@ -179,9 +179,12 @@ int smallk_pad_K(int M);
 bool smallk_config_ok(int prec, int cfg, int K);  // exists for prec and runs without scratch at K
 
 // timing hook helpers (api.hip): bracket a launch with events when enabled
-enum TimedKernel { TK_GEMM = 0, TK_KSG = 1, TK_PAIRS = 2, TK_STD = 3 };
+enum TimedKernel { TK_GEMM = 0, TK_KSG = 1, TK_PAIRS = 2, TK_STD = 3, TK_AGG = 4, TK_COUNT = 5 };
 void timing_begin(corr_ctx* ctx, int which, hipStream_t s);
 void timing_end(corr_ctx* ctx, int which, hipStream_t s);
+
+// aggregate.hip: member-major level of f^3 block means (f a power of two <= 64)
+int launch_block_means(const corr_field& A, int f, int out_dtype, void* out, int64_t out_stride, hipStream_t s);
 
 // small utility kernels (api.hip)
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

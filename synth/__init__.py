@@ -22,3 +22,4 @@ from .fields import (  # noqa: F401
     region_pairs_uniform,
     smooth_noise,
 )
+from .device import smooth_field_torch  # noqa: F401,E402
