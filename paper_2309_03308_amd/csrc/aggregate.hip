@@ -9,6 +9,7 @@
 // with cross-lane shuffles and the first of them writes the block's mean.
 // 64 is a multiple of f (f a power of two <= 64), so no block straddles two
 // wavefronts. Loads go out 16 at a time before any of them is summed.
+// A vector variant (below) serves f = 2 and 4 when rows are aligned.
 #include "common.h"
 
 namespace corr {
@@ -28,13 +29,14 @@ __device__ __forceinline__ double load_as_double<_Float16>(const _Float16* p) {
 
 template <typename T>
 __device__ __forceinline__ void store_from_double(T* p, double v);
+// Streaming (non-temporal) stores: the level is not read back by this kernel.
 template <>
 __device__ __forceinline__ void store_from_double<float>(float* p, double v) {
-    *p = (float)v;
+    __builtin_nontemporal_store((float)v, p);
 }
 template <>
 __device__ __forceinline__ void store_from_double<_Float16>(_Float16* p, double v) {
-    *p = (_Float16)v;  // one rounding, FP64 -> FP16
+    __builtin_nontemporal_store((_Float16)v, p);  // one rounding, FP64 -> FP16
 }
 
 // Members handled by one wavefront item: enough independent loads in flight
@@ -126,8 +128,83 @@ __global__ __launch_bounds__(256) void block_means_kernel(AggArgs a) {
     }
 }
 
+// f = 2 or 4 with whole blocks along x and F-element-aligned rows: lane l
+// owns block X = 64 s + l and reads its f columns as one f-wide vector from
+// each of the block's f x f rows, sums them in FP64 and writes the mean: no
+// cross-lane step, and each wavefront's stores form one contiguous run.
+template <typename Tin, typename Tout, int F>
+__global__ __launch_bounds__(256) void block_means_vec_kernel(AggArgs a) {
+    using V = Tin __attribute__((ext_vector_type(F)));
+    constexpr int MB = F == 2 ? 2 : 1;
+    constexpr int L = MB * F * F;  // vector loads per lane per item
+    const int lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= a.items) return;
+    int64_t r = item;
+    const int seg = (int)(r % a.nseg);
+    r /= a.nseg;
+    const int Y = (int)(r % a.NY);
+    r /= a.NY;
+    const int Z = (int)(r % a.NZ);
+    const int m0 = (int)(r / a.NZ) * MB;
+
+    const int X = seg * 64 + lane;
+    const bool xin = X < a.NX;
+    const int ylim = min(F, a.ny - F * Y);
+    const int zlim = min(F, a.nz - F * Z);
+    const Tin* col = (const Tin*)a.in + (int64_t)F * min(X, a.NX - 1);
+    const int64_t plane = (int64_t)a.nx * a.ny;
+
+    V v[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int j = t / (F * F), dz = (t % (F * F)) / F, dy = t % F;
+        const int m = min(m0 + j, a.M - 1);
+        const int y = min(F * Y + dy, a.ny - 1), z = min(F * Z + dz, a.nz - 1);
+        v[t] = __builtin_nontemporal_load((const V*)(col + (int64_t)m * a.in_stride + plane * z + (int64_t)a.nx * y));
+    }
+    if (!xin) return;
+    const double cnt = (double)(F * ylim * zlim);
+    Tout* out = (Tout*)a.out;
+    const int64_t q = X + (int64_t)a.NX * (Y + (int64_t)a.NY * Z);
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = j * F * F; t < (j + 1) * F * F; ++t) {
+            const int dz = (t % (F * F)) / F, dy = t % F;
+            if (dz < zlim && dy < ylim) {
+#pragma unroll
+                for (int e = 0; e < F; ++e) acc += (double)(float)v[t][e];
+            }
+        }
+        if (m0 + j < a.M) store_from_double(out + (int64_t)(m0 + j) * a.out_stride + q, acc / cnt);
+    }
+}
+
+template <typename Tin, typename Tout, int F>
+bool vec_ok(const AggArgs& a) {
+    if constexpr (F != 2 && F != 4) {
+        return false;
+    } else {
+        return a.nx % F == 0 && a.in_stride % F == 0 && ((uintptr_t)a.in % (F * sizeof(Tin))) == 0;
+    }
+}
+
 template <typename Tin, typename Tout, int F>
 int launch_f(AggArgs a, hipStream_t s) {
+    if constexpr (F == 2 || F == 4) {
+        if (vec_ok<Tin, Tout, F>(a)) {
+            constexpr int MB = F == 2 ? 2 : 1;
+            a.nseg = (a.NX + 63) / 64;
+            a.items = (int64_t)a.nseg * a.NY * a.NZ * ((a.M + MB - 1) / MB);
+            const int64_t wgs = (a.items + 3) / 4;
+            if (wgs > 0x7fffffffLL) return fail(CORR_EUNSUPPORTED, "block means: grid too large");
+            block_means_vec_kernel<Tin, Tout, F><<<dim3((unsigned)wgs), 256, 0, s>>>(a);
+            CORR_LAUNCH_CHECK();
+            return CORR_OK;
+        }
+    }
     constexpr int MB = members_per_item<F>();
     a.items = (int64_t)a.nseg * a.NY * a.NZ * ((a.M + MB - 1) / MB);
     const int64_t wgs = (a.items + 3) / 4;
@@ -166,7 +243,7 @@ int launch_block_means(const corr_field& A, int f, int out_dtype, void* out, int
     a.NY = (A.ny + f - 1) / f;
     a.NZ = (A.nz + f - 1) / f;
     a.out_stride = out_stride ? out_stride : (int64_t)a.NX * a.NY * a.NZ;
-    a.nseg = (A.nx + 63) / 64;
+    a.nseg = (A.nx + 63) / 64;  // the vector kernel recomputes it over blocks
     const bool in16 = A.dtype == CORR_F16, out16 = out_dtype == CORR_F16;
     if (!in16 && !out16) return launch_io<float, float>(a, f, s);
     if (!in16 && out16) return launch_io<float, _Float16>(a, f, s);

@@ -4,7 +4,8 @@ Bars: FP32 output within one FP32 ulp of the FP64 mean (both sides sum in
 FP64 and round once; only the summation order differs), FP16 output within
 one FP16 ulp. Cases: ragged grids that span several 64-column segments and
 end in partial blocks on every axis, f in {1, 2, 4, 8, 64}, FP16 input,
-padded member strides, error handling; at the 180-member 640 x 704 x 64 shape
+padded member strides (both kernels: the vector one for f = 2, 4 over
+aligned rows whole in x, the lane-group one otherwise), error handling; at the 180-member 640 x 704 x 64 shape
 the benchmark times, sampled blocks (edges included) are checked one by one.
 The composed path -- brick maxima estimated on a level -- is compared with
 the oracle's maxima on the oracle's own level.
@@ -43,17 +44,20 @@ def _ulps(got, ref, dt):
     return np.abs(got.astype(np.float64) - ref) / sp
 
 
-@pytest.mark.parametrize("dims", [(37, 13, 5), (130, 7, 9), (64, 64, 4), (1, 3, 2)])
+# nx a multiple of f with aligned rows takes the vector kernel (f = 2, 4);
+# the odd member stride P + 7 and the ragged nx take the lane-group kernel
+@pytest.mark.parametrize("dims", [(37, 13, 5), (130, 7, 9), (64, 64, 4), (36, 5, 3), (1, 3, 2)])
 @pytest.mark.parametrize("f", [1, 2, 4, 8, 64])
 @pytest.mark.parametrize("io", ["f32-f32", "f32-f16", "f16-f32", "f16-f16"])
-def test_block_means_parity(env, dims, f, io):
+@pytest.mark.parametrize("pad", [0, 7])
+def test_block_means_parity(env, dims, f, io, pad):
     torch, pc, ctx = env["torch"], env["pc"], env["ctx"]
     nx, ny, nz = dims
     din, dout = io.split("-")
     rng = np.random.default_rng(hash((dims, f)) & 0xffff)
     M, P = 5, nx * ny * nz
     data = (rng.standard_normal((M, P)) * 3 + 1).astype(np.float32 if din == "f32" else np.float16)
-    padded = np.zeros((M, P + 7), data.dtype)  # member stride P + 7
+    padded = np.zeros((M, P + pad), data.dtype)  # member stride P + pad
     padded[:, :P] = data
     A = pc.Field(torch.from_numpy(padded).cuda(), nx, ny, nz)
     lvl = ctx.corr_block_means(A, f, dout)
