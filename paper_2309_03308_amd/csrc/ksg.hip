@@ -7,12 +7,18 @@
 // psi(M) + psi(k) - mean_i[psi(n_x,i + 1) + psi(n_y,i + 1)].
 //
 // Design (gfx950, wave64, VALU-bound):
-//  - a wave owns a chunk of PW consecutive pairs and stages, per pair, the
-//    joint samples as (x_j, y_j), twice in a row (j = 0..M-1, then again),
-//    and both marginals sorted ascending (sorted once per point, not per
-//    pair, by sort_rows_kernel);
-//  - the chunk's PW*M (pair, sample) items are laid densely over the lanes,
-//    so no lane idles when M is not a multiple of 64;
+//  - every wave streams through its own contiguous range of pairs; the
+//    range's (pair, sample) items are laid densely over the lanes, 64 per
+//    trip, so a trip may cover the tail of one pair and the head of the next
+//    and no lane idles except in the range's last trip. Waves never wait for
+//    one another (the only workgroup barrier is the digamma table load);
+//  - a pair is staged into a small per-wave ring of LDS slots just before the
+//    first trip that reaches it: its joint samples (x_j, y_j) twice in a row
+//    (j = 0..M-1, then again) and both marginals sorted ascending (sorted once
+//    per point, not per pair, by sort_rows_kernel); after the trip holding its
+//    last item the wave reduces its digamma terms and the slot is reused;
+//  - for large M the items of each pair are padded to a multiple of 64 so a
+//    trip never straddles two pairs and one slot per wave suffices;
 //  - eps_i: item i reads the M-1 samples that follow it in the doubled row
 //    (i+1 .. i+M-1), so its own zero distance never enters the selection;
 //    the KP >= k smallest distances are kept in registers; inserting d is
@@ -24,17 +30,15 @@
 //    branch-free binary searches find it (the run includes j = i exactly when
 //    eps_i > 0, which is subtracted). This replaces M distance tests with
 //    2 log2(M) probes and gives the same integer bit for bit;
-//  - each item's (n_x, n_y) is kept in LDS; one lane per pair then sums the
-//    FP64 digamma terms (integer-argument table) in sample order, so MI is
-//    deterministic.
+//  - each item's (n_x, n_y) is kept in LDS; the wave then sums a pair's FP64
+//    digamma terms (integer-argument table) in a fixed order (lane l takes
+//    samples l, l + 64, ..., then a fixed xor tree), so MI is deterministic.
 // Distances are plain FP32 subtract/abs/max (no contraction). The unit is
 // compiled with IEEE mode off: every operand is finite or +inf, for which
 // min/max/med3 give the same results, and no NaN quieting is needed.
 #include "common.h"
 
 namespace corr {
-
-constexpr int KSG_WAVES = 4;
 
 template <int KP>
 __device__ __forceinline__ void topk_insert(float (&t)[KP], float d) {
@@ -65,169 +69,186 @@ __device__ __forceinline__ void run_counts(const float* sx, const float* sy, int
 }
 
 struct KsgLayout {
-    int mdup;       // float2 entries of the doubled sample row (2 M)
-    int p2;         // power of two > M (sorted marginals)
-    int pw;         // pairs per wave chunk (divides 64)
-    int slot_f;     // floats per pair slot
-    int wave_f;     // floats per wave (slots, packed counts, pair info)
-    int psi_f;      // floats of the block-shared digamma table
+    int mdup;     // float2 entries of the doubled sample row (2 M)
+    int p2;       // power of two > M (sorted marginals)
+    int stride;   // items per pair: M (packed) or M rounded up to 64 (padded)
+    int ring;     // LDS pair slots per wave
+    int slot_f;   // floats per pair slot
+    int wave_f;   // floats per wave (slots, packed counts, pair info)
+    int psi_f;    // floats of the block-shared digamma table
+    int waves;    // waves per workgroup
 };
 
+// Orders LDS accesses of one wave across lanes (a compiler barrier; the LDS
+// executes one wave's operations in issue order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KP>
-__global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L) {
+__global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L, int64_t n_waves) {
     extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // block-shared: digamma table psi[0..M] (FP64), then per wave: pair slots,
-    // packed counts, per-pair (la, lb, flags)
+    // packed counts, per-pair (la, lb, state, in_max)
     double* psi = reinterpret_cast<double*>(lds_f);
-    float* wbase = lds_f + L.psi_f + wave * L.wave_f;
-    uint32_t* cnt = reinterpret_cast<uint32_t*>(wbase + L.pw * L.slot_f);  // packed n_x | n_y << 16
-    int* pinfo = reinterpret_cast<int*>(cnt + L.pw * a.M);                 // [pw][4]: la, lb, state, in_max
-    for (int v = threadIdx.x; v <= a.M; v += 256) psi[v] = a.psi[v];
-    const int M = a.M;
-    const int k = a.k;
+    for (int v = threadIdx.x; v <= a.M; v += blockDim.x) psi[v] = a.psi[v];
+    __syncthreads();  // the only workgroup barrier: waves are independent from here
+
+    const int M = a.M, k = a.k, S = L.stride, R = L.ring;
+    const int64_t gw = (int64_t)blockIdx.x * L.waves + wave;
+    const int64_t p_begin = n_total * gw / n_waves, p_end = n_total * (gw + 1) / n_waves;
+    const int np = (int)(p_end - p_begin);
+    if (np <= 0) return;
+    float* wb = lds_f + L.psi_f + wave * L.wave_f;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(wb + R * L.slot_f);  // [R][M] packed n_x | n_y << 16
+    int* info = reinterpret_cast<int*>(cnt + R * M);                 // [R][4]
     const int64_t nb = a.bb.count();
     const float inf = __builtin_inff();
     unsigned long long best = 0;
     uint32_t n_in_max = 0;
-    const int64_t chunk_pairs = (int64_t)KSG_WAVES * L.pw;
 
-    for (int64_t base = (int64_t)blockIdx.x * chunk_pairs; base < n_total; base += (int64_t)gridDim.x * chunk_pairs) {
-        const int64_t wbase_pair = base + (int64_t)wave * L.pw;
-        // ---- per-pair index math, one lane per pair
-        // state: 0 = nothing to evaluate, 1 = evaluate, 2 = constant point (MI 0)
-        if (lane < L.pw) {
-            const int64_t t = wbase_pair + lane;
+    // per lane: local pair q, sample i, ring slot r of item U + lane
+    int q = lane / S, i = lane - (lane / S) * S, r = q % R;
+    int staged = 0, done = 0;
+    const int64_t n_items = (int64_t)np * S;
+    for (int64_t U = 0; U < n_items; U += 64) {
+        // ---- stage every pair this trip reaches (uniform loop)
+        const int need = min(__builtin_amdgcn_readlane(q, 63), np - 1);
+        for (; staged <= need; ++staged) {
+            const int sr = staged % R;
+            const int64_t t = p_begin + staged;
             int la = -1, lb = -1, state = 0, in_max = 0;
-            if (t < n_total) {
-                bool same = false;
-                if (a.pairs) {
-                    const int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
-                    la = a.whole_a ? ga : (int)a.ba.local(ga);
-                    lb = a.whole_b ? gb : (int)a.bb.local(gb);
-                    same = ga == gb;
-                } else {
-                    const int32_t tt = (int32_t)t, nb32 = (int32_t)nb;
-                    la = tt / nb32;
-                    lb = tt - la * nb32;
-                    same = a.ba.global(la) == a.bb.global(lb);
+            bool same = false;
+            if (a.pairs) {
+                const int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
+                la = a.whole_a ? ga : (int)a.ba.local(ga);
+                lb = a.whole_b ? gb : (int)a.bb.local(gb);
+                same = ga == gb;
+            } else {
+                const int32_t tt = (int32_t)t, nb32 = (int32_t)nb;
+                la = tt / nb32;
+                lb = tt - la * nb32;
+                same = a.ba.global(la) == a.bb.global(lb);
+            }
+            // state: 0 = nothing to evaluate, 1 = evaluate, 2 = constant point (MI 0)
+            if (la >= 0 && lb >= 0) {
+                state = 1;
+                if (a.inv_a && (a.inv_a[la] == 0.0f || a.inv_b[lb] == 0.0f)) state = 2;
+                in_max = (a.key != nullptr) && !(a.same_field && same);
+            }
+            if (lane == 0) {
+                info[4 * sr] = la;
+                info[4 * sr + 1] = lb;
+                info[4 * sr + 2] = state;
+                info[4 * sr + 3] = in_max;
+            }
+            if (state == 1) {
+                float* slot = wb + sr * L.slot_f;
+                float2* xy = reinterpret_cast<float2*>(slot);
+                float* sx = slot + 2 * L.mdup;
+                float* sy = sx + L.p2;
+                const float* xa = a.za + (int64_t)la * a.ld;
+                const float* yb = a.zb + (int64_t)lb * a.ld;
+                const float* sxa = a.sa + (int64_t)la * L.p2;
+                const float* syb = a.sb + (int64_t)lb * L.p2;
+                for (int j = lane; j < M; j += 64) {
+                    const float2 v = make_float2(xa[j], yb[j]);
+                    xy[j] = v;
+                    xy[j + M] = v;
                 }
-                if (la >= 0 && lb >= 0) {
-                    state = 1;
-                    if (a.inv_a && (a.inv_a[la] == 0.0f || a.inv_b[lb] == 0.0f)) state = 2;
-                    in_max = (a.key != nullptr) && !(a.same_field && same);
+                for (int j = lane; j < L.p2; j += 64) {
+                    sx[j] = sxa[j];
+                    sy[j] = syb[j];
                 }
             }
-            int* pi = pinfo + 4 * lane;
-            pi[0] = la;
-            pi[1] = lb;
-            pi[2] = state;
-            pi[3] = in_max;
         }
-        __syncthreads();
-        // ---- stage the wave's pairs (all waves reach every barrier)
-        for (int q = 0; q < L.pw; ++q) {
-            const int* pi = pinfo + 4 * q;
-            if (pi[2] != 1) continue;
-            float* slot = wbase + q * L.slot_f;
-            float2* xy = reinterpret_cast<float2*>(slot);
-            float* sx = slot + 2 * L.mdup;
-            float* sy = sx + L.p2;
-            const int64_t la = pi[0], lb = pi[1];
-            const float* xa = a.za + la * a.ld;
-            const float* yb = a.zb + lb * a.ld;
-            const float* sxa = a.sa + la * L.p2;
-            const float* syb = a.sb + lb * L.p2;
-            for (int j = lane; j < M; j += 64) {
-                const float2 v = make_float2(xa[j], yb[j]);
-                xy[j] = v;
-                xy[j + M] = v;
-            }
-            for (int j = lane; j < L.p2; j += 64) {
-                sx[j] = sxa[j];
-                sy[j] = syb[j];
-            }
-        }
-        __syncthreads();
-        // ---- items: u = q * M + i over the wave's pairs
-        const int n_items = L.pw * M;
-        for (int u0 = 0; u0 < n_items; u0 += 64) {
-            const int u = u0 + lane;
-            const int uc = u < n_items ? u : n_items - 1;
-            const int q = uc / M, i = uc - q * M;
-            const float* slot = wbase + q * L.slot_f;
-            const float2* row = reinterpret_cast<const float2*>(slot);
-            const float2 me = row[i];
-            const float2* nbr = row + i + 1;  // the M-1 other samples, in cyclic order
-            float tk[KP];
+        wave_lds_sync();
+
+        // ---- one item per lane
+        const bool act = q < np && i < M;
+        const int ic = i < M ? i : M - 1;
+        const float* slot = wb + r * L.slot_f;
+        const float2* row = reinterpret_cast<const float2*>(slot);
+        const float2 me = row[ic];
+        const float2* nbr = row + ic + 1;  // the M-1 other samples, in cyclic order
+        float tk[KP];
 #pragma unroll
-            for (int p = 0; p < KP; ++p) tk[p] = inf;
-            int t = 0;
-            for (; t + 4 <= M - 1; t += 4) {  // four reads per trip: immediate LDS offsets
-                const float2 v0 = nbr[t], v1 = nbr[t + 1], v2 = nbr[t + 2], v3 = nbr[t + 3];
-                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
-                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
-                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
-                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v3.x), fabsf(me.y - v3.y)));
-            }
-            for (; t < M - 1; ++t) {
-                const float2 v = nbr[t];
-                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
-            }
-            float eps = tk[0];
-#pragma unroll
-            for (int p = 1; p < KP; ++p) eps = (p == k - 1) ? tk[p] : eps;
-            const float* sx = slot + 2 * L.mdup;
-            const float* sy = sx + L.p2;
-            const int self = eps > 0.0f ? 1 : 0;
-            int nx, ny;
-            run_counts(sx, sy, L.p2, me.x, me.y, eps, nx, ny);
-            nx -= self;
-            ny -= self;
-            nx = nx < 0 ? 0 : nx;
-            ny = ny < 0 ? 0 : ny;
-            if (u < n_items) {
-                cnt[u] = (uint32_t)nx | ((uint32_t)ny << 16);
-                const int64_t t = wbase_pair + q;
-                if (a.counts_out && pinfo[4 * q + 2] == 1)
-                    reinterpret_cast<int2*>(a.counts_out)[t * M + i] = make_int2(nx, ny);
-            }
+        for (int p = 0; p < KP; ++p) tk[p] = inf;
+        int t = 0;
+        for (; t + 4 <= M - 1; t += 4) {  // four reads per trip: immediate LDS offsets
+            const float2 v0 = nbr[t], v1 = nbr[t + 1], v2 = nbr[t + 2], v3 = nbr[t + 3];
+            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
+            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
+            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
+            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v3.x), fabsf(me.y - v3.y)));
         }
-        __syncthreads();
-        // ---- per pair: G = 64 / pw lanes sum the digamma terms; lane r of a
-        // group takes samples r, r + G, ... in order, then a fixed xor tree
-        // combines the group -- the same order on every run
-        {
-            const int G = 64 / L.pw;
-            const int q = lane / G, r = lane - q * G;
-            const int* pi = pinfo + 4 * q;
+        for (; t < M - 1; ++t) {
+            const float2 v = nbr[t];
+            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
+        }
+        float eps = tk[KP - 1];
+        if (k != KP) {
+#pragma unroll
+            for (int p = 0; p < KP - 1; ++p) eps = (p == k - 1) ? tk[p] : eps;
+        }
+        const float* sx = slot + 2 * L.mdup;
+        const float* sy = sx + L.p2;
+        const int self = eps > 0.0f ? 1 : 0;
+        int nx, ny;
+        run_counts(sx, sy, L.p2, me.x, me.y, eps, nx, ny);
+        nx -= self;
+        ny -= self;
+        nx = nx < 0 ? 0 : nx;
+        ny = ny < 0 ? 0 : ny;
+        if (act) {
+            cnt[r * M + i] = (uint32_t)nx | ((uint32_t)ny << 16);
+            if (a.counts_out && info[4 * r + 2] == 1)
+                reinterpret_cast<int2*>(a.counts_out)[(p_begin + q) * M + i] = make_int2(nx, ny);
+        }
+        wave_lds_sync();
+
+        // ---- advance every lane by 64 items, then retire the pairs now complete
+        i += 64;
+        while (i >= S) {
+            i -= S;
+            ++q;
+            r = (r + 1 == R) ? 0 : r + 1;
+        }
+        const int complete = min(__builtin_amdgcn_readlane(q, 0), np);
+        for (; done < complete; ++done) {
+            const int dr = done % R;
+            const int state = info[4 * dr + 2];
             double acc = 0.0;
-            if (pi[2] == 1) {
-                const uint32_t* cq = cnt + q * M;
-                for (int i = r; i < M; i += G) {
-                    const uint32_t c = cq[i];
+            if (state == 1) {
+                const uint32_t* cq = cnt + dr * M;
+                for (int j = lane; j < M; j += 64) {
+                    const uint32_t c = cq[j];
                     acc += psi[(c & 0xffffu) + 1] + psi[(c >> 16) + 1];
                 }
             }
-            for (int off = G >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            const int64_t t = wbase_pair + q;
-            if (r == 0 && t < n_total) {
-                const int state = pi[2];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            const int64_t tp = p_begin + done;
+            if (lane == 0) {
                 float mi = 0.0f;
                 if (state == 1) mi = (float)(psi[M] + psi[k] - acc / (double)M);
-                if (a.mi_out) a.mi_out[t] = mi;
-                if (pi[3] && state != 0) {
-                    const unsigned long long key = make_key(mi, (uint32_t)((int64_t)pi[0] * nb + pi[1]), 0u);
+                if (a.mi_out) a.mi_out[tp] = mi;
+                if (info[4 * dr + 3] && state != 0) {
+                    const unsigned long long key =
+                        make_key(mi, (uint32_t)((int64_t)info[4 * dr] * nb + info[4 * dr + 1]), 0u);
                     best = key > best ? key : best;
                     ++n_in_max;
                 }
             }
-            if (a.counts_out && t < n_total && pi[2] != 1) {
-                int2* c = reinterpret_cast<int2*>(a.counts_out) + t * M;
-                for (int i = r; i < M; i += G) c[i] = make_int2(0, 0);
+            if (a.counts_out && state != 1) {
+                int2* c = reinterpret_cast<int2*>(a.counts_out) + tp * M;
+                for (int j = lane; j < M; j += 64) c[j] = make_int2(0, 0);
             }
         }
-        __syncthreads();  // slots and terms are rewritten by the next chunk
+        wave_lds_sync();
     }
     if (a.key) {
 #pragma unroll
@@ -296,37 +317,70 @@ int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* ou
     return CORR_OK;
 }
 
-// Pairs per wave chunk: dense items (pw * M close to a multiple of 64) traded
-// against LDS per wave (occupancy). pw <= 0 picks the default.
-int ksg_default_pw(int M) { return M >= 512 ? 1 : (M >= 192 ? 2 : (M >= 48 ? 4 : 16)); }
+// Mapping knob (the autotuner's candidate): workgroups per CU of the
+// resident grid, capped by what the kernel's registers and LDS allow.
+// <= 0 picks the cap.
+int ksg_default_pw(int M) {
+    (void)M;
+    return 0;
+}
 
-static KsgLayout ksg_layout(int M, int pw) {
+static KsgLayout ksg_layout(int M) {
     KsgLayout L;
     L.mdup = 2 * M;
     L.p2 = ksg_p2(M);
-    L.pw = pw > 0 ? pw : ksg_default_pw(M);
-    L.slot_f = 2 * L.mdup + 2 * L.p2;
-    L.slot_f = (L.slot_f + 3) & ~3;
-    L.wave_f = L.pw * L.slot_f + L.pw * M + 4 * L.pw;  // + packed counts, pair info
-    L.wave_f = (L.wave_f + 3) & ~3;
+    L.slot_f = (2 * L.mdup + 2 * L.p2 + 3) & ~3;
     L.psi_f = (2 * (M + 1) + 3) & ~3;
+    auto wave_floats = [&](int ring) { return (ring * L.slot_f + ring * M + 4 * ring + 3) & ~3; };
+    // packed items (no idle lanes) while four waves of it fit next to each
+    // other in LDS with room for two workgroups, else padded items
+    const int ring_packed = (63 + M - 1) / M + 1;
+    if ((size_t)(4 * wave_floats(ring_packed) + L.psi_f) * 4 <= 80 * 1024) {
+        L.stride = M;
+        L.ring = ring_packed;
+    } else {
+        L.stride = (M + 63) / 64 * 64;
+        L.ring = 1;
+    }
+    L.wave_f = wave_floats(L.ring);
+    L.waves = 4;
+    while (L.waves > 1 && (size_t)(L.waves * L.wave_f + L.psi_f) * 4 > 160 * 1024) --L.waves;
     return L;
 }
 
 size_t ksg_lds_bytes(int M, int pw) {
-    const KsgLayout L = ksg_layout(M, pw);
-    return ((size_t)KSG_WAVES * L.wave_f + L.psi_f) * sizeof(float);
+    (void)pw;
+    const KsgLayout L = ksg_layout(M);
+    return ((size_t)L.waves * L.wave_f + L.psi_f) * sizeof(float);
 }
 
 template <int KP>
-static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, dim3 grid, size_t lds, hipStream_t s) {
+static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
     static bool attr = false;
     if (!attr) {
         CORR_HIP(hipFuncSetAttribute((const void*)ksg_kernel<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      160 * 1024));
         attr = true;
     }
-    ksg_kernel<KP><<<grid, 256, lds, s>>>(a, n_total, L);
+    const int threads = 64 * L.waves;
+    static size_t cached_lds = 0;
+    static int cached_threads = 0, cached_per_cu = 0;
+    if (lds != cached_lds || threads != cached_threads) {
+        int n = 0;
+        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)ksg_kernel<KP>, threads, lds));
+        cached_lds = lds;
+        cached_threads = threads;
+        cached_per_cu = n;
+    }
+    int per_cu = cached_per_cu;
+    if (per_cu < 1) per_cu = 1;
+    if (a.pw > 0 && a.pw < per_cu) per_cu = a.pw;
+    // a resident grid: every wave's pair range starts at once
+    int64_t blocks = (int64_t)num_cus * per_cu;
+    const int64_t min_blocks = (n_total + L.waves - 1) / L.waves;  // at least one pair per wave
+    if (blocks > min_blocks) blocks = min_blocks;
+    const int64_t n_waves = blocks * L.waves;
+    ksg_kernel<KP><<<dim3((unsigned)blocks), threads, lds, s>>>(a, n_total, L, n_waves);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -334,23 +388,18 @@ static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, dim3
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     int64_t n_total = a.pairs ? a.n : a.ba.count() * a.bb.count();
     if (n_total == 0) return CORR_OK;
-    const KsgLayout L = ksg_layout(a.M, a.pw);
-    if (64 % L.pw) return fail(CORR_EINVAL, "KSG: pairs per wave must divide 64");
+    const KsgLayout L = ksg_layout(a.M);
     const size_t lds = ksg_lds_bytes(a.M, a.pw);
     if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
-    const int64_t chunk_pairs = (int64_t)KSG_WAVES * L.pw;
-    int64_t blocks = (n_total + chunk_pairs - 1) / chunk_pairs;
-    int64_t cap = (int64_t)num_cus * 8;
-    dim3 grid((unsigned)(blocks < cap ? blocks : cap));
     // selection width: the smallest instantiated KP >= k
     const int k = a.k;
-    if (k == 10) return launch_kp<10>(a, n_total, L, grid, lds, s);
-    if (k <= 4) return launch_kp<4>(a, n_total, L, grid, lds, s);
-    if (k <= 8) return launch_kp<8>(a, n_total, L, grid, lds, s);
-    if (k <= 12) return launch_kp<12>(a, n_total, L, grid, lds, s);
-    if (k <= 16) return launch_kp<16>(a, n_total, L, grid, lds, s);
-    if (k <= 24) return launch_kp<24>(a, n_total, L, grid, lds, s);
-    return launch_kp<32>(a, n_total, L, grid, lds, s);
+    if (k == 10) return launch_kp<10>(a, n_total, L, num_cus, lds, s);
+    if (k <= 4) return launch_kp<4>(a, n_total, L, num_cus, lds, s);
+    if (k <= 8) return launch_kp<8>(a, n_total, L, num_cus, lds, s);
+    if (k <= 12) return launch_kp<12>(a, n_total, L, num_cus, lds, s);
+    if (k <= 16) return launch_kp<16>(a, n_total, L, num_cus, lds, s);
+    if (k <= 24) return launch_kp<24>(a, n_total, L, num_cus, lds, s);
+    return launch_kp<32>(a, n_total, L, num_cus, lds, s);
 }
 
 }  // namespace corr
