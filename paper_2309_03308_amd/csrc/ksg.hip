@@ -52,17 +52,31 @@ __device__ __forceinline__ void topk_insert(float (&t)[KP], float d) {
 // once: lo = number of leading s with fl32(x - s) >= eps, hi = number of
 // leading s with fl32(x - s) > -eps; the j with |fl32(x - x_j)| < eps are
 // exactly the hi - lo entries in between. The four searches are interleaved
-// so their LDS reads overlap.
+// so their LDS reads overlap. P2 > 0 fixes the row length at compile time
+// (the probes then use immediate LDS offsets); P2 == 0 reads it from p2.
+template <int P2>
 __device__ __forceinline__ void run_counts(const float* sx, const float* sy, int p2, float x, float y, float eps,
                                            int& cx, int& cy) {
     int lx = 0, ux = 0, ly = 0, uy = 0;
-    for (int step = p2 >> 1; step >= 1; step >>= 1) {
-        const float a0 = sx[lx + step - 1], a1 = sx[ux + step - 1];
-        const float b0 = sy[ly + step - 1], b1 = sy[uy + step - 1];
-        lx += (x - a0 < eps) ? 0 : step;
-        ux += (x - a1 > -eps) ? step : 0;
-        ly += (y - b0 < eps) ? 0 : step;
-        uy += (y - b1 > -eps) ? step : 0;
+    if constexpr (P2 > 0) {
+#pragma unroll
+        for (int step = P2 >> 1; step >= 1; step >>= 1) {
+            const float a0 = sx[lx + step - 1], a1 = sx[ux + step - 1];
+            const float b0 = sy[ly + step - 1], b1 = sy[uy + step - 1];
+            lx += (x - a0 < eps) ? 0 : step;
+            ux += (x - a1 > -eps) ? step : 0;
+            ly += (y - b0 < eps) ? 0 : step;
+            uy += (y - b1 > -eps) ? step : 0;
+        }
+    } else {
+        for (int step = p2 >> 1; step >= 1; step >>= 1) {
+            const float a0 = sx[lx + step - 1], a1 = sx[ux + step - 1];
+            const float b0 = sy[ly + step - 1], b1 = sy[uy + step - 1];
+            lx += (x - a0 < eps) ? 0 : step;
+            ux += (x - a1 > -eps) ? step : 0;
+            ly += (y - b0 < eps) ? 0 : step;
+            uy += (y - b1 > -eps) ? step : 0;
+        }
     }
     cx = ux - lx;
     cy = uy - ly;
@@ -87,7 +101,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KP>
+template <int KP, int P2>
 __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L, int64_t n_waves) {
     extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -177,17 +191,20 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
         float tk[KP];
 #pragma unroll
         for (int p = 0; p < KP; ++p) tk[p] = inf;
-        int t = 0;
-        for (; t + 4 <= M - 1; t += 4) {  // four reads per trip: immediate LDS offsets
+        const int t4 = (M - 1) & ~3;
+        for (int t = 0; t < t4; t += 4) {  // four reads per trip: immediate LDS offsets
             const float2 v0 = nbr[t], v1 = nbr[t + 1], v2 = nbr[t + 2], v3 = nbr[t + 3];
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v3.x), fabsf(me.y - v3.y)));
         }
-        for (; t < M - 1; ++t) {
-            const float2 v = nbr[t];
-            topk_insert<KP>(tk, fmaxf(fabsf(me.x - v.x), fabsf(me.y - v.y)));
+        {  // the last (M - 1) % 4 samples, without a loop (wave-uniform tests)
+            const int rem = (M - 1) & 3;
+            const float2* tail = nbr + t4;
+            if (rem >= 1) topk_insert<KP>(tk, fmaxf(fabsf(me.x - tail[0].x), fabsf(me.y - tail[0].y)));
+            if (rem >= 2) topk_insert<KP>(tk, fmaxf(fabsf(me.x - tail[1].x), fabsf(me.y - tail[1].y)));
+            if (rem >= 3) topk_insert<KP>(tk, fmaxf(fabsf(me.x - tail[2].x), fabsf(me.y - tail[2].y)));
         }
         float eps = tk[KP - 1];
         if (k != KP) {
@@ -198,7 +215,7 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
         const float* sy = sx + L.p2;
         const int self = eps > 0.0f ? 1 : 0;
         int nx, ny;
-        run_counts(sx, sy, L.p2, me.x, me.y, eps, nx, ny);
+        run_counts<P2>(sx, sy, L.p2, me.x, me.y, eps, nx, ny);
         nx -= self;
         ny -= self;
         nx = nx < 0 ? 0 : nx;
@@ -354,12 +371,12 @@ size_t ksg_lds_bytes(int M, int pw) {
     return ((size_t)L.waves * L.wave_f + L.psi_f) * sizeof(float);
 }
 
-template <int KP>
+template <int KP, int P2>
 static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
+    const void* fn = (const void*)ksg_kernel<KP, P2>;
     static bool attr = false;
     if (!attr) {
-        CORR_HIP(hipFuncSetAttribute((const void*)ksg_kernel<KP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
+        CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr = true;
     }
     const int threads = 64 * L.waves;
@@ -367,7 +384,7 @@ static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int 
     static int cached_threads = 0, cached_per_cu = 0;
     if (lds != cached_lds || threads != cached_threads) {
         int n = 0;
-        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)ksg_kernel<KP>, threads, lds));
+        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds));
         cached_lds = lds;
         cached_threads = threads;
         cached_per_cu = n;
@@ -380,9 +397,19 @@ static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int 
     const int64_t min_blocks = (n_total + L.waves - 1) / L.waves;  // at least one pair per wave
     if (blocks > min_blocks) blocks = min_blocks;
     const int64_t n_waves = blocks * L.waves;
-    ksg_kernel<KP><<<dim3((unsigned)blocks), threads, lds, s>>>(a, n_total, L, n_waves);
+    ksg_kernel<KP, P2><<<dim3((unsigned)blocks), threads, lds, s>>>(a, n_total, L, n_waves);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
+}
+
+template <int KP>
+static int launch_p2(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
+    switch (L.p2) {
+        case 64: return launch_kp<KP, 64>(a, n_total, L, num_cus, lds, s);
+        case 128: return launch_kp<KP, 128>(a, n_total, L, num_cus, lds, s);
+        case 256: return launch_kp<KP, 256>(a, n_total, L, num_cus, lds, s);
+        default: return launch_kp<KP, 0>(a, n_total, L, num_cus, lds, s);
+    }
 }
 
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
@@ -393,13 +420,13 @@ int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
     // selection width: the smallest instantiated KP >= k
     const int k = a.k;
-    if (k == 10) return launch_kp<10>(a, n_total, L, num_cus, lds, s);
-    if (k <= 4) return launch_kp<4>(a, n_total, L, num_cus, lds, s);
-    if (k <= 8) return launch_kp<8>(a, n_total, L, num_cus, lds, s);
-    if (k <= 12) return launch_kp<12>(a, n_total, L, num_cus, lds, s);
-    if (k <= 16) return launch_kp<16>(a, n_total, L, num_cus, lds, s);
-    if (k <= 24) return launch_kp<24>(a, n_total, L, num_cus, lds, s);
-    return launch_kp<32>(a, n_total, L, num_cus, lds, s);
+    if (k == 10) return launch_p2<10>(a, n_total, L, num_cus, lds, s);
+    if (k <= 4) return launch_p2<4>(a, n_total, L, num_cus, lds, s);
+    if (k <= 8) return launch_p2<8>(a, n_total, L, num_cus, lds, s);
+    if (k <= 12) return launch_p2<12>(a, n_total, L, num_cus, lds, s);
+    if (k <= 16) return launch_p2<16>(a, n_total, L, num_cus, lds, s);
+    if (k <= 24) return launch_p2<24>(a, n_total, L, num_cus, lds, s);
+    return launch_p2<32>(a, n_total, L, num_cus, lds, s);
 }
 
 }  // namespace corr
