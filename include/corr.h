@@ -68,6 +68,13 @@ enum corr_prec {
 
 enum corr_measure { CORR_PEARSON = 0, CORR_KSG = 1 };
 
+/* Sample sequences over a brick pair's 6-D box (Sec. 3.1): uniform
+ * pseudo-random, Halton, and the (six-dimensional) plastic sequence. */
+enum corr_sampler { CORR_SAMPLE_UNIFORM = 0, CORR_SAMPLE_HALTON = 1, CORR_SAMPLE_PLASTIC = 2 };
+
+/* Estimation strategy for a brick pair (Sec. 5, sampling strategy). */
+enum corr_strategy { CORR_STRATEGY_BOS = 0, CORR_STRATEGY_RANDOM = 1, CORR_STRATEGY_EXHAUSTIVE = 2 };
+
 /* corr_ksg_mi_pairs flag: use the stored values as the KSG samples instead
  * of z-scoring each point first. */
 #define CORR_KSG_RAW 1u
@@ -196,6 +203,53 @@ int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
  * table; malformed or out-of-range records are skipped. */
 int corr_tune_save(corr_ctx* ctx, const char* path);
 int corr_tune_load(corr_ctx* ctx, const char* path);
+
+/*
+ * Samples of brick pairs (Sec. 3.1: random or quasi-random sampling of the
+ * 6-D box x, y, z in brick A and x, y, z in brick B). For region pair p
+ * (regions[region_pairs[2p]], regions[region_pairs[2p+1]]) and sample
+ * s in [0, n_samples): u in [0,1)^6 from `sampler` (enum corr_sampler), cell
+ * c_j = min(floor(u_j d_j), d_j - 1) with d = the two regions' extents, and
+ * out[2 (p n + s)] / out[2 (p n + s) + 1] = the global indices of the A and B
+ * points (A's grid for the first, B's for the second).
+ *   uniform: u_j = Philox4x64-10 word 0 of counter (p, 5, s, j), key
+ *            (seed, 0x636F7272), as (w >> 11) 2^-53;
+ *   Halton:  u_j = frac(h_{b_j}(s + 1) + c_j), bases 2, 3, 5, 7, 11, 13;
+ *   plastic: u_j = frac(c_j + (s + 1) alpha_j), alpha_j = phi^-j by repeated
+ *            division, phi = 1.1127756842787055 (root of x^7 = x + 1);
+ *   c_j = the uniform of counter (p, 6, 0, j).
+ * regions / region_pairs: HOST arrays ([n_regions], [n_pairs][2]); out:
+ * device int32 [n_pairs][n_samples][2]. CORR_EINVAL for bad indices or
+ * regions outside their grids, n_pairs < 0, n_samples < 0 or
+ * n_pairs * n_samples >= 2^31; CORR_EUNSUPPORTED for an unknown sampler.
+ * Synchronises `stream` (the pair boxes are staged from host memory).
+ */
+int corr_sample_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const corr_region* regions,
+                      int32_t n_regions, const int32_t* region_pairs, int32_t n_pairs, int sampler,
+                      int32_t n_samples, uint64_t seed, int32_t* out, corr_stream_t stream);
+
+/*
+ * Sampled maxima of many brick pairs at once: the samples of
+ * corr_sample_pairs, evaluated with corr_pearson_pairs (objective |r|, in
+ * precision `prec`) or corr_ksg_mi_pairs (objective MI, k neighbours), and
+ * per pair the earliest sample of the largest objective. Within one field
+ * (A and B the same) a sample of a point with itself is skipped, as in the
+ * exhaustive maxima. out: HOST corr_max[n_pairs] (n_evaluated = the samples
+ * counted). Synchronises `stream`.
+ */
+int corr_sampled_max(corr_ctx* ctx, const corr_field* A, const corr_field* B, const corr_region* regions,
+                     int32_t n_regions, const int32_t* region_pairs, int32_t n_pairs, int measure, int prec,
+                     int32_t k, int sampler, int32_t n_samples, uint64_t seed, corr_max* out,
+                     corr_stream_t stream);
+
+/*
+ * Strategy for a pair of bricks with na and nb points (Sec. 5, sampling
+ * strategy): CORR_STRATEGY_BOS when both hold at least 16^3 points, else
+ * CORR_STRATEGY_EXHAUSTIVE when na * nb / pairs_per_s <= budget_s (the
+ * paper's 5 s), else CORR_STRATEGY_RANDOM. pairs_per_s: the exhaustive
+ * evaluation rate of the measure at hand (> 0). strategy: HOST int.
+ */
+int corr_choose_strategy(int64_t na, int64_t nb, double pairs_per_s, double budget_s, int32_t* strategy);
 
 /*
  * One level of the mean tree (Sec. 4, sampling from spatial aggregates):

@@ -21,7 +21,8 @@ Readings (the paper names the sequences but not their construction):
   u_j = frac(c_j + (s + 1) alpha_j) with alpha_j = phi^-j, phi the real root
   above 1 of x^7 = x + 1 (d = 6), the same per-pair shift;
 * the maximum of a brick pair over its samples uses the region-maximum rule
-  (objective |r| for Pearson, MI for KSG, the earliest of equal values);
+  (objective |r| for Pearson, MI for KSG, the earliest of equal values, and
+  within one field no point paired with itself);
 * strategy: BOS when both bricks hold at least 16^3 points, else the
   exhaustive computation when |A| |B| / rate is at most the time budget
   (5 s), else uniform random sampling.
@@ -101,11 +102,19 @@ def sample_points(sampler, seed, pair, ra, rb, nx, ny, n):
     return np.stack([pa, pb], 1).astype(np.int32)
 
 
-def sampled_max(values, pairs, use_abs=True):
-    """(value, signed value, pA, pB) of the earliest maximum over the samples."""
-    v = np.abs(values) if use_abs else np.asarray(values)
+def sampled_max(values, pairs, use_abs=True, same_field=False):
+    """(value, signed value, pA, pB, samples counted) of the earliest maximum
+    over the samples; within one field a point paired with itself is no
+    sample (the region-maximum rule)."""
+    values = np.asarray(values)
+    keep = np.ones(len(values), bool)
+    if same_field:
+        keep = pairs[:, 0] != pairs[:, 1]
+    if not keep.any():
+        return 0.0, 0.0, -1, -1, 0
+    v = np.where(keep, np.abs(values) if use_abs else values, -np.inf)
     i = int(np.argmax(v))  # first of equal maxima
-    return float(v[i]), float(values[i]), int(pairs[i, 0]), int(pairs[i, 1])
+    return float(v[i]), float(values[i]), int(pairs[i, 0]), int(pairs[i, 1]), int(keep.sum())
 
 
 def choose_strategy(na: int, nb: int, pairs_per_s: float, budget_s: float = 5.0, bos_min: int = 16 ** 3) -> int:

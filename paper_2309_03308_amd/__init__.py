@@ -9,8 +9,10 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
+
 from . import _lib
-from ._lib import CorrError, bos_config, corr_field, corr_max, corr_region, PREC, MEASURE  # noqa: F401
+from ._lib import CorrError, bos_config, corr_field, corr_max, corr_region, PREC, MEASURE, SAMPLER, STRATEGY  # noqa: F401
 
 
 def _torch():
@@ -166,6 +168,40 @@ class Context:
         return dict(value=out.value, signed_value=out.signed_value, pa=out.pa, pb=out.pb,
                     n_evaluated=out.n_evaluated)
 
+    # ------------------------------------------------------------------ sampling
+    @staticmethod
+    def _region_arrays(regions, region_pairs):
+        regs = [region(*r) if isinstance(r, tuple) else r for r in regions]
+        ra = (corr_region * max(1, len(regs)))(*regs)
+        rp = np.ascontiguousarray(np.asarray(region_pairs, dtype=np.int32).reshape(-1, 2))
+        return ra, len(regs), rp
+
+    def corr_sample_pairs(self, A: Field, regions, region_pairs, sampler="uniform", n=100, seed=0, B: Field = None,
+                          stream=None):
+        """Sample point pairs of brick pairs: device int32 (n_pairs, n, 2) global indices."""
+        torch = _torch()
+        B = A if B is None else B
+        ra, nr, rp = self._region_arrays(regions, region_pairs)
+        out = torch.empty((rp.shape[0], int(n), 2), dtype=torch.int32, device=A.data.device)
+        _lib.check(self.L.corr_sample_pairs(self.h, ctypes.byref(A.c), ctypes.byref(B.c), ctypes.cast(ra, ctypes.c_void_p),
+                                            nr, rp.ctypes.data_as(ctypes.c_void_p), rp.shape[0], SAMPLER[sampler],
+                                            int(n), int(seed) & (2 ** 64 - 1), ctypes.c_void_p(out.data_ptr()),
+                                            _stream_ptr(stream)))
+        return out
+
+    def corr_sampled_max(self, A: Field, regions, region_pairs, measure="pearson", prec="f32", k=10,
+                         sampler="uniform", n=100, seed=0, B: Field = None, stream=None):
+        """Sampled maxima of many brick pairs: a list of dicts like corr_region_max's."""
+        B = A if B is None else B
+        ra, nr, rp = self._region_arrays(regions, region_pairs)
+        res = (corr_max * max(1, rp.shape[0]))()
+        _lib.check(self.L.corr_sampled_max(self.h, ctypes.byref(A.c), ctypes.byref(B.c), ctypes.cast(ra, ctypes.c_void_p),
+                                           nr, rp.ctypes.data_as(ctypes.c_void_p), rp.shape[0], MEASURE[measure],
+                                           PREC[prec], int(k), SAMPLER[sampler], int(n), int(seed) & (2 ** 64 - 1),
+                                           ctypes.cast(res, ctypes.c_void_p), _stream_ptr(stream)))
+        return [dict(value=r.value, signed_value=r.signed_value, pa=r.pa, pb=r.pb, n_evaluated=r.n_evaluated)
+                for r in res[:rp.shape[0]]]
+
     # ------------------------------------------------------------------ mean tree
     def corr_block_means(self, A: Field, f: int, dtype="f32", out=None, stream=None) -> Field:
         """One mean-tree level: the field of f^3 block means (a new Field, or one over `out`)."""
@@ -187,6 +223,46 @@ class Context:
     def mean_tree(self, A: Field, factors=(2, 4), dtype="f32", stream=None) -> dict:
         """Levels of the mean tree, each computed from the initial data: {f: Field}."""
         return {int(f): self.corr_block_means(A, f, dtype, stream=stream) for f in factors}
+
+
+# Exhaustive evaluation rates used by choose_strategy when the caller gives
+# none (point pairs per second on one MI355X, measured at M = 100 and scaled
+# with the work per pair: M for Pearson, M^2 for KSG).
+EXHAUSTIVE_RATE_M100 = {"pearson": 4.5e12, "ksg": 2.2e8}
+
+
+def exhaustive_rate(measure: str, M: int) -> float:
+    r = EXHAUSTIVE_RATE_M100[measure]
+    return r * (100.0 / M) if measure == "pearson" else r * (100.0 / M) ** 2
+
+
+def choose_strategy(na: int, nb: int, pairs_per_s: float, budget_s: float = 5.0) -> str:
+    """"bos", "random" or "exhaustive" for bricks of na and nb points (Sec. 5)."""
+    st = ctypes.c_int32()
+    _lib.check(_lib.load().corr_choose_strategy(int(na), int(nb), float(pairs_per_s), float(budget_s),
+                                                ctypes.byref(st)))
+    return STRATEGY[st.value]
+
+
+def brick_max(ctx: Context, A: Field, ra: corr_region, rb: corr_region, measure="pearson", prec="f16x3", k=10,
+              budget_s=5.0, n_samples=100, seed=0, pairs_per_s=None, B: Field = None, bos_cfg=None):
+    """The maximum of one brick pair by the strategy of Sec. 5: BOS for bricks of
+    at least 16^3 points, else every point pair when that fits the time budget,
+    else uniform random sampling. Returns (strategy, corr_region_max-style dict)."""
+    B = A if B is None else B
+    na, nb = ra.dx * ra.dy * ra.dz, rb.dx * rb.dy * rb.dz
+    rate = exhaustive_rate(measure, A.M) if pairs_per_s is None else pairs_per_s
+    st = choose_strategy(na, nb, rate, budget_s)
+    if st == "exhaustive":
+        return st, ctx.corr_region_max(A, ra, rb, measure, prec, k, B=B)
+    if st == "random":
+        return st, ctx.corr_sampled_max(A, [ra, rb], [(0, 1)], measure, prec, k, "uniform", n_samples, seed, B=B)[0]
+    bos = Bos(ctx, A, [ra, rb], [(0, 1)], bos_cfg if bos_cfg is not None else bos_defaults(measure=measure, k=k), B=B)
+    try:
+        bos.bos_run()
+        return st, bos.bos_results()[0]
+    finally:
+        bos.close()
 
 
 def level_dims(nx, ny, nz, f):

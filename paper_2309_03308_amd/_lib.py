@@ -17,6 +17,8 @@ CORR_OK, CORR_EINVAL, CORR_EUNSUPPORTED, CORR_ENOMEM, CORR_EHIP, CORR_ESTATE = r
 CORR_F32, CORR_F16 = 0, 1
 PREC = {"f32": 0, "f16": 1, "bf16": 2, "f16x3": 3, "bf16x3": 4}
 MEASURE = {"pearson": 0, "ksg": 1}
+SAMPLER = {"uniform": 0, "halton": 1, "plastic": 2}
+STRATEGY = {0: "bos", 1: "random", 2: "exhaustive"}
 CORR_KSG_RAW = 1
 
 
@@ -85,6 +87,11 @@ SIGNATURES = {
     "bos_destroy": (None, [_P]),
     "corr_kernel_time_ms": (_I, [_P, _I, ctypes.POINTER(ctypes.c_float)]),
     "corr_block_means": (_I, [_P, ctypes.POINTER(corr_field), _I, _I, _P, _I64, _P]),
+    "corr_sample_pairs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I32, _P, _I32, _I,
+                               _I32, ctypes.c_uint64, _P, _P]),
+    "corr_sampled_max": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I32, _P, _I32, _I,
+                              _I, _I32, _I, _I32, ctypes.c_uint64, _P, _P]),
+    "corr_choose_strategy": (_I, [_I64, _I64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_I32)]),
     "prop_mlp_create": (_I, [_P, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "prop_mlp_num_params": (_I, [_P, ctypes.POINTER(_I64)]),
     "prop_mlp_get_params": (_I, [_P, _P]),

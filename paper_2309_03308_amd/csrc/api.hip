@@ -746,4 +746,103 @@ int corr_block_means(corr_ctx* ctx, const corr_field* A, int f, int out_dtype, v
     return rc;
 }
 
+// ---- sampling (Sec. 3.1) and strategy (Sec. 5) ------------------------------
+static int check_sampling_args(const corr_field* A, const corr_field* B, const corr_region* regions,
+                               int32_t n_regions, const int32_t* region_pairs, int32_t n_pairs, int sampler,
+                               int32_t n_samples) {
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if (n_pairs < 0 || n_samples < 0) return fail(CORR_EINVAL, "negative pair or sample count");
+    if ((int64_t)n_pairs * n_samples >= (int64_t(1) << 31)) return fail(CORR_EINVAL, "too many samples");
+    if (sampler < CORR_SAMPLE_UNIFORM || sampler > CORR_SAMPLE_PLASTIC) return fail(CORR_EUNSUPPORTED, "sampler");
+    if (n_pairs > 0 && (!regions || !region_pairs || n_regions < 1)) return fail(CORR_EINVAL, "null regions");
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        const int32_t ia = region_pairs[2 * p], ib = region_pairs[2 * p + 1];
+        if (ia < 0 || ia >= n_regions || ib < 0 || ib >= n_regions) return fail(CORR_EINVAL, "region index");
+        if ((rc = check_region(&regions[ia], *A, "region of A"))) return rc;
+        if ((rc = check_region(&regions[ib], *B, "region of B"))) return rc;
+    }
+    return CORR_OK;
+}
+
+static int stage_samples(corr_ctx* ctx, const corr_field* A, const corr_field* B, const corr_region* regions,
+                         const int32_t* region_pairs, int32_t n_pairs, int sampler, int32_t n_samples, uint64_t seed,
+                         int32_t* out, hipStream_t s) {
+    const size_t bb = sample_boxes_bytes(n_pairs);
+    void* dbox = nullptr;
+    int rc = ws_get(ctx, WS_SBOXES, bb + sizeof(corr_max) * (size_t)n_pairs, s, &dbox);
+    if (rc) return rc;
+    std::vector<unsigned char> hbox(bb);
+    fill_sample_boxes(hbox.data(), regions, region_pairs, n_pairs, *A, *B);
+    CORR_HIP(hipMemcpyAsync(dbox, hbox.data(), bb, hipMemcpyHostToDevice, s));
+    rc = launch_sample_pairs(dbox, n_pairs, n_samples, sampler, seed, out, s);
+    if (rc) return rc;
+    CORR_HIP(hipStreamSynchronize(s));  // hbox is released on return
+    return CORR_OK;
+}
+
+int corr_sample_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, const corr_region* regions,
+                      int32_t n_regions, const int32_t* region_pairs, int32_t n_pairs, int sampler,
+                      int32_t n_samples, uint64_t seed, int32_t* out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_sampling_args(A, B, regions, n_regions, region_pairs, n_pairs, sampler, n_samples);
+    if (rc) return rc;
+    if ((int64_t)n_pairs * n_samples == 0) return CORR_OK;
+    if (!out) return fail(CORR_EINVAL, "null output");
+    return stage_samples(ctx, A, B, regions, region_pairs, n_pairs, sampler, n_samples, seed, out,
+                         (hipStream_t)stream);
+}
+
+int corr_sampled_max(corr_ctx* ctx, const corr_field* A, const corr_field* B, const corr_region* regions,
+                     int32_t n_regions, const int32_t* region_pairs, int32_t n_pairs, int measure, int prec,
+                     int32_t k, int sampler, int32_t n_samples, uint64_t seed, corr_max* out,
+                     corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_sampling_args(A, B, regions, n_regions, region_pairs, n_pairs, sampler, n_samples);
+    if (rc) return rc;
+    if (measure != CORR_PEARSON && measure != CORR_KSG) return fail(CORR_EINVAL, "unknown measure");
+    if (measure == CORR_KSG && (k < 1 || k > A->M - 1)) return fail(CORR_EINVAL, "k outside [1, M-1]");
+    if (n_pairs == 0) return CORR_OK;
+    if (!out) return fail(CORR_EINVAL, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)n_pairs * n_samples;
+    void *dpairs = nullptr, *dvals = nullptr, *dbox = nullptr;
+    if ((rc = ws_get(ctx, WS_SAMPLES, sizeof(int32_t) * 2 * (size_t)(n > 0 ? n : 1), s, &dpairs))) return rc;
+    if ((rc = ws_get(ctx, WS_SVALUES, sizeof(float) * (size_t)(n > 0 ? n : 1), s, &dvals))) return rc;
+    if (n > 0) {
+        rc = stage_samples(ctx, A, B, regions, region_pairs, n_pairs, sampler, n_samples, seed, (int32_t*)dpairs, s);
+        if (rc) return rc;
+        if (measure == CORR_PEARSON)
+            rc = corr_pearson_pairs(ctx, A, B, (const int32_t*)dpairs, n, prec, (float*)dvals, stream);
+        else
+            rc = corr_ksg_mi_pairs(ctx, A, B, (const int32_t*)dpairs, n, k, 0, (float*)dvals, nullptr, stream);
+        if (rc) return rc;
+    }
+    if ((rc = ws_get(ctx, WS_SBOXES, sample_boxes_bytes(n_pairs) + sizeof(corr_max) * (size_t)n_pairs, s, &dbox)))
+        return rc;
+    corr_max* dres = (corr_max*)((unsigned char*)dbox + sample_boxes_bytes(n_pairs));
+    rc = launch_segment_max((const float*)dvals, (const int32_t*)dpairs, n_pairs, n_samples,
+                            measure == CORR_PEARSON ? 1 : 0, same_field(*A, *B) ? 1 : 0, dres, s);
+    if (rc) return rc;
+    CORR_HIP(hipMemcpyAsync(out, dres, sizeof(corr_max) * (size_t)n_pairs, hipMemcpyDeviceToHost, s));
+    CORR_HIP(hipStreamSynchronize(s));
+    return CORR_OK;
+}
+
+int corr_choose_strategy(int64_t na, int64_t nb, double pairs_per_s, double budget_s, int32_t* strategy) {
+    if (!strategy) return fail(CORR_EINVAL, "null output");
+    if (na < 1 || nb < 1 || !(pairs_per_s > 0.0) || !(budget_s >= 0.0))
+        return fail(CORR_EINVAL, "bad brick sizes, rate or budget");
+    const int64_t bos_min = 16 * 16 * 16;
+    if (na >= bos_min && nb >= bos_min)
+        *strategy = CORR_STRATEGY_BOS;
+    else if ((double)na * (double)nb <= budget_s * pairs_per_s)
+        *strategy = CORR_STRATEGY_EXHAUSTIVE;
+    else
+        *strategy = CORR_STRATEGY_RANDOM;
+    return CORR_OK;
+}
+
 }  // extern "C"

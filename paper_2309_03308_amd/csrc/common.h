@@ -54,7 +54,7 @@ struct Box {
 // ---- workspace --------------------------------------------------------------
 enum WsSlot {
     WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
-    WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_COUNT
+    WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_SAMPLES, WS_SVALUES, WS_SBOXES, WS_COUNT
 };
 
 }  // namespace corr
@@ -185,6 +185,15 @@ void timing_end(corr_ctx* ctx, int which, hipStream_t s);
 
 // aggregate.hip: member-major level of f^3 block means (f a power of two <= 64)
 int launch_block_means(const corr_field& A, int f, int out_dtype, void* out, int64_t out_stride, hipStream_t s);
+
+// sampling.hip: brick-pair samples and per-pair maxima of sample values
+int launch_sample_pairs(const void* boxes, int32_t n_pairs, int32_t n, int sampler, uint64_t seed, int32_t* out,
+                        hipStream_t s);
+int launch_segment_max(const float* values, const int32_t* pairs, int32_t n_pairs, int32_t n, int use_abs,
+                       int same_field, corr_max* out, hipStream_t s);
+size_t sample_boxes_bytes(int32_t n_pairs);
+void fill_sample_boxes(void* host, const corr_region* regions, const int32_t* region_pairs, int32_t n_pairs,
+                       const corr_field& A, const corr_field& B);
 
 // small utility kernels (api.hip)
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

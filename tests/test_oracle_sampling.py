@@ -87,8 +87,11 @@ def test_sample_points_are_in_the_bricks():
 def test_sampled_max_is_first_argmax():
     vals = np.array([0.1, -0.7, 0.7, 0.3])
     pairs = np.array([[1, 2], [3, 4], [5, 6], [7, 8]])
-    assert SR.sampled_max(vals, pairs) == (0.7, -0.7, 3, 4)
-    assert SR.sampled_max(vals, pairs, use_abs=False) == (0.7, 0.7, 5, 6)
+    assert SR.sampled_max(vals, pairs) == (0.7, -0.7, 3, 4, 4)
+    assert SR.sampled_max(vals, pairs, use_abs=False) == (0.7, 0.7, 5, 6, 4)
+    selfp = np.array([[1, 2], [4, 4], [5, 6], [7, 8]])
+    assert SR.sampled_max(vals, selfp, same_field=True) == (0.7, 0.7, 5, 6, 3)
+    assert SR.sampled_max(vals, selfp) == (0.7, -0.7, 4, 4, 4)
 
 
 def test_strategy_thresholds():
