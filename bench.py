@@ -126,13 +126,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
-    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree", "meantree-dev"],
+    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree", "meantree-dev", "samplers"],
                     help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
                          "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates; onetoall: one "
                          "reference point against every point of a 250x352x20 field (M=100) and of the "
                          "128x128x32 field (M=1000); meantree: mean-tree levels f=2,4 of a 180-member "
                          "640x704x64 field; meantree-dev: deviation of brick maxima on those levels over the 3828 "
-                         "brick pairs of the 352x256x20 field")
+                         "brick pairs of the 352x256x20 field; samplers: convergence of uniform / Halton / plastic "
+                         "sampled maxima over those pairs and on 6-D Gaussian test objectives")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -159,6 +160,8 @@ def main():
         return run_meantree(args, torch, synth, pc)
     if args.workload == "meantree-dev":
         return run_meantree_dev(args, torch, synth, pc)
+    if args.workload == "samplers":
+        return run_samplers(args, torch, synth, pc)
     return run_focus(args, torch, synth, pc)
 
 
@@ -406,6 +409,91 @@ def run_meantree_dev(args, torch, synth, pc):
                             "mean_max_f1_planted": float(np.mean(maxima[1][planted])) if planted.any() else None,
                             "s_all_pairs": {f"f{k}": v for k, v in tmax.items()}})
     line["steps"], line["warmup"] = 1, 0
+    print(json.dumps(line), flush=True)
+
+
+def _gauss6(rng, dims):
+    """A 6-D Gaussian test objective over a brick pair's cell box (a random
+    mean in the box, a random rotation, standard deviations of 4 to 8 cells):
+    the objective value at cells, its exact maximum over the integer cells (within
+    3 cells of the mean per axis, which a condition number of 4 guarantees) and its
+    minimum (a corner of the box)."""
+    d = np.asarray(dims, np.float64)
+    mu = rng.uniform(0, 1, 6) * (d - 1)
+    q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    prec = q @ np.diag(1.0 / rng.uniform(4.0, 8.0, 6) ** 2) @ q.T
+
+    def f(c):
+        x = np.asarray(c, np.float64) - mu
+        return np.exp(-0.5 * np.einsum("ni,ij,nj->n", x, prec, x))
+
+    base = np.round(mu).astype(np.int64)
+    g = np.stack(np.meshgrid(*[np.arange(-3, 4)] * 6, indexing="ij"), -1).reshape(-1, 6) + base
+    g = g[np.all((g >= 0) & (g < np.asarray(dims)), axis=1)]
+    corners = np.array([[(dims[j] - 1) * ((m >> j) & 1) for j in range(6)] for m in range(64)])
+    return f, float(f(g).max()), float(f(corners).min())
+
+
+def run_samplers(args, torch, synth, pc):
+    """Uniform / Halton / plastic sampling (Sec. 3.1): maxima against exhaustive truth."""
+    ctx = pc.Context(0)
+    e = synth.make_cfg3()
+    F = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    regs = [r.as_tuple() for r in e.regions]
+    rp = synth.region_pair_list(len(regs))
+    t0 = time.perf_counter()
+    truth = np.array([ctx.corr_region_max(F, pc.region(*regs[a]), pc.region(*regs[b]), "pearson", "f16x3")["value"]
+                      for a, b in rp])
+    t_ex = time.perf_counter() - t0
+    ns = (25, 50, 100, 200, 400, 800, 1600)
+    seeds = (0, 1, 2)
+    curves, times = {}, {}
+    for smp in ("uniform", "halton", "plastic"):
+        curves[smp], times[smp] = {}, {}
+        for n in ns:
+            errs, tt = [], []
+            for sd in seeds:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                res = ctx.corr_sampled_max(F, regs, rp, "pearson", "f32", 10, smp, n, sd)
+                tt.append(time.perf_counter() - t1)
+                v = np.array([r["value"] for r in res])
+                errs.append(float(np.mean((truth - v) / truth)))
+            curves[smp][n] = float(np.mean(errs))
+            times[smp][n] = float(np.median(tt))
+        print(f"samplers: pearson {smp} done", file=sys.stderr, flush=True)
+    # KSG: mean sampled maximum (exhaustive KSG truth is out of reach: 4.2e8 pairs per brick pair)
+    ksg = {}
+    for smp in ("uniform", "halton", "plastic"):
+        ksg[smp] = {n: float(np.mean([r["value"] for r in ctx.corr_sampled_max(F, regs, rp, "ksg", "f32", 10, smp, n, 0)]))
+                    for n in (25, 100, 400)}
+    # Gaussian test objectives on 1000 brick pairs of 32^3 cells (the samples come from the library)
+    G = pc.Field(torch.zeros((2, 32 * 32 * 32), device="cuda"), 32, 32, 32)
+    rng = np.random.default_rng(2309)
+    objs = [_gauss6(rng, (32,) * 6) for _ in range(1000)]
+    gauss = {}
+    for smp in ("uniform", "halton", "plastic"):
+        gauss[smp] = {}
+        for n in (25, 50, 100, 200, 400, 800):
+            cells = ctx.corr_sample_pairs(G, [(0, 0, 0, 32, 32, 32)], np.zeros((1000, 2), np.int32), smp, n, 5)
+            c = cells.cpu().numpy().astype(np.int64)
+            err = []
+            for p, (f, mx, mn) in enumerate(objs):
+                pa, pb = c[p, :, 0], c[p, :, 1]
+                cc = np.stack([pa % 32, (pa // 32) % 32, pa // 1024, pb % 32, (pb // 32) % 32, pb // 1024], 1)
+                err.append((mx - f(cc).max()) / (mx - mn))
+            gauss[smp][n] = float(np.mean(err))
+    ctx.close()
+    n_ref = 100
+    line = _line(args, len(rp) * n_ref / times["uniform"][n_ref], times["uniform"][n_ref] * 1e3,
+                 {"workload": "sampled Pearson maxima (FP32) of the 3828 pairs of 32x32x20 bricks of the 352x256x20 "
+                              "M=100 field, 100 uniform samples per pair (batched); convergence of the three "
+                              "samplers against exhaustive FP16x3 maxima", "members": 100, "brick_pairs": int(len(rp))},
+                 breakdown={"exhaustive_truth_s": t_ex,
+                            "mean_rel_error_pearson": curves, "call_s": times,
+                            "mean_sampled_max_ksg": ksg,
+                            "gauss6_mean_normalized_error": gauss})
+    line["steps"], line["warmup"] = len(seeds), 0
     print(json.dumps(line), flush=True)
 
 
