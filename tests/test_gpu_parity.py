@@ -153,6 +153,26 @@ def test_ksg_ties_and_small_M(ctx, pc, torch):
             assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
 
 
+@pytest.mark.parametrize("M,k,n", [(2, 1, 60000), (3, 2, 60000), (17, 4, 60000), (63, 10, 40000), (64, 10, 40000),
+                                   (100, 10, 40000), (130, 10, 30000), (300, 10, 12000)])
+def test_ksg_streams_many_pairs_per_wave(ctx, pc, torch, M, k, n):
+    # enough pairs that every wave streams several of them through its LDS
+    # ring: packed items crossing pair boundaries (M < 64 puts several pairs
+    # in one trip) and padded items for large M
+    _say(f"ksg stream M={M} k={k} n={n}")
+    rng = np.random.default_rng(M)
+    data = rng.standard_normal((M, 500)).astype(np.float32)
+    data[:, 7] = 1.5  # a constant point: MI 0, counts 0
+    pairs = rng.integers(0, 500, (n, 2)).astype(np.int32)
+    pairs[::997, 0] = 7
+    f = pc.Field(dev(torch, data), 500, 1, 1)
+    mi, cnt = ctx.corr_ksg_mi_pairs(f, dev(torch, pairs), k=k, counts=True)
+    mi_ref, cnt_ref = oracle.ksg_pairs(data, pairs, k)
+    cnt = cnt.cpu().numpy()
+    assert np.array_equal(cnt, cnt_ref), f"{int((cnt != cnt_ref).sum())} counts differ"
+    assert np.max(np.abs(mi.cpu().numpy() - mi_ref)) <= MI_TOL
+
+
 # ------------------------------------------------------------ region maxima
 @pytest.mark.parametrize("prec", MODES)
 def test_region_max_pearson_cfg1(ctx, pc, torch, cfg1, prec):
