@@ -18,7 +18,10 @@
 //    per point, not per pair, by sort_rows_kernel); after the trip holding its
 //    last item the wave reduces its digamma terms and the slot is reused;
 //  - for large M the items of each pair are padded to a multiple of 64 so a
-//    trip never straddles two pairs and one slot per wave suffices;
+//    trip never straddles two pairs and one slot per wave suffices; each
+//    lane then sums its own samples' digamma terms, so the layout keeps no
+//    count array and takes the table from global memory, and the smaller
+//    workgroups fit more waves per CU;
 //  - eps_i: item i reads the M-1 samples that follow it in the doubled row
 //    (i+1 .. i+M-1), so its own zero distance never enters the selection;
 //    the KP >= k smallest distances are kept in registers; inserting d is
@@ -86,10 +89,11 @@ struct KsgLayout {
     int mdup;     // float2 entries of the doubled sample row (2 M)
     int p2;       // power of two > M (sorted marginals)
     int stride;   // items per pair: M (packed) or M rounded up to 64 (padded)
+    int pad;      // padded items: one slot, per-lane digamma sums, table in global memory
     int ring;     // LDS pair slots per wave
     int slot_f;   // floats per pair slot
     int wave_f;   // floats per wave (slots, packed counts, pair info)
-    int psi_f;    // floats of the block-shared digamma table
+    int psi_f;    // floats of the block-shared digamma table (0 when padded)
     int waves;    // waves per workgroup
 };
 
@@ -101,15 +105,25 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KP, int P2>
+// PAD: items padded to a multiple of 64 per pair (large M). Each trip then
+// belongs to one pair, lane l meets samples l, l + 64, ... in order and sums
+// their digamma terms itself (the order of the packed reduction), so no count
+// array is kept and the digamma table is read from global memory: the
+// smaller LDS footprint lets more waves share a CU.
+template <int KP, int P2, bool PAD>
 __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, KsgLayout L, int64_t n_waves) {
     extern __shared__ __attribute__((aligned(16))) float lds_f[];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // block-shared: digamma table psi[0..M] (FP64), then per wave: pair slots,
-    // packed counts, per-pair (la, lb, state, in_max)
-    double* psi = reinterpret_cast<double*>(lds_f);
-    for (int v = threadIdx.x; v <= a.M; v += blockDim.x) psi[v] = a.psi[v];
-    __syncthreads();  // the only workgroup barrier: waves are independent from here
+    // block-shared: digamma table psi[0..M] (FP64, packed layout only), then
+    // per wave: pair slots, packed counts (packed layout only), per-pair
+    // (la, lb, state, in_max)
+    const double* psi = a.psi;
+    if constexpr (!PAD) {
+        double* spsi = reinterpret_cast<double*>(lds_f);
+        for (int v = threadIdx.x; v <= a.M; v += blockDim.x) spsi[v] = a.psi[v];
+        __syncthreads();  // the only workgroup barrier: waves are independent from here
+        psi = spsi;
+    }
 
     const int M = a.M, k = a.k, S = L.stride, R = L.ring;
     const int64_t gw = (int64_t)blockIdx.x * L.waves + wave;
@@ -118,7 +132,8 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
     if (np <= 0) return;
     float* wb = lds_f + L.psi_f + wave * L.wave_f;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(wb + R * L.slot_f);  // [R][M] packed n_x | n_y << 16
-    int* info = reinterpret_cast<int*>(cnt + R * M);                 // [R][4]
+    int* info = reinterpret_cast<int*>(cnt + (PAD ? 0 : R * M));     // [R][4]
+    double lacc = 0.0;                                               // PAD: this lane's digamma sum
     const int64_t nb = a.bb.count();
     const float inf = __builtin_inff();
     unsigned long long best = 0;
@@ -192,8 +207,20 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
 #pragma unroll
         for (int p = 0; p < KP; ++p) tk[p] = inf;
         const int t4 = (M - 1) & ~3;
-        for (int t = 0; t < t4; t += 4) {  // four reads per trip: immediate LDS offsets
-            const float2 v0 = nbr[t], v1 = nbr[t + 1], v2 = nbr[t + 2], v3 = nbr[t + 3];
+        if (t4 > 0) {  // groups of four samples; the next group's LDS reads are
+                       // issued before the current group's selection work
+            float2 v0 = nbr[0], v1 = nbr[1], v2 = nbr[2], v3 = nbr[3];
+            for (int t = 4; t < t4; t += 4) {
+                const float2 w0 = nbr[t], w1 = nbr[t + 1], w2 = nbr[t + 2], w3 = nbr[t + 3];
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
+                topk_insert<KP>(tk, fmaxf(fabsf(me.x - v3.x), fabsf(me.y - v3.y)));
+                v0 = w0;
+                v1 = w1;
+                v2 = w2;
+                v3 = w3;
+            }
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v0.x), fabsf(me.y - v0.y)));
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v1.x), fabsf(me.y - v1.y)));
             topk_insert<KP>(tk, fmaxf(fabsf(me.x - v2.x), fabsf(me.y - v2.y)));
@@ -221,9 +248,13 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
         nx = nx < 0 ? 0 : nx;
         ny = ny < 0 ? 0 : ny;
         if (act) {
-            cnt[r * M + i] = (uint32_t)nx | ((uint32_t)ny << 16);
-            if (a.counts_out && info[4 * r + 2] == 1)
-                reinterpret_cast<int2*>(a.counts_out)[(p_begin + q) * M + i] = make_int2(nx, ny);
+            const bool eval = info[4 * r + 2] == 1;
+            if constexpr (PAD) {
+                if (eval) lacc += psi[nx + 1] + psi[ny + 1];
+            } else {
+                cnt[r * M + i] = (uint32_t)nx | ((uint32_t)ny << 16);
+            }
+            if (a.counts_out && eval) reinterpret_cast<int2*>(a.counts_out)[(p_begin + q) * M + i] = make_int2(nx, ny);
         }
         wave_lds_sync();
 
@@ -239,7 +270,10 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             const int dr = done % R;
             const int state = info[4 * dr + 2];
             double acc = 0.0;
-            if (state == 1) {
+            if constexpr (PAD) {
+                acc = lacc;
+                lacc = 0.0;
+            } else if (state == 1) {
                 const uint32_t* cq = cnt + dr * M;
                 for (int j = lane; j < M; j += 64) {
                     const uint32_t c = cq[j];
@@ -347,20 +381,37 @@ static KsgLayout ksg_layout(int M) {
     L.mdup = 2 * M;
     L.p2 = ksg_p2(M);
     L.slot_f = (2 * L.mdup + 2 * L.p2 + 3) & ~3;
-    L.psi_f = (2 * (M + 1) + 3) & ~3;
-    auto wave_floats = [&](int ring) { return (ring * L.slot_f + ring * M + 4 * ring + 3) & ~3; };
     // packed items (no idle lanes) while four waves of it fit next to each
     // other in LDS with room for two workgroups, else padded items
     const int ring_packed = (63 + M - 1) / M + 1;
-    if ((size_t)(4 * wave_floats(ring_packed) + L.psi_f) * 4 <= 80 * 1024) {
+    const int psi_packed = (2 * (M + 1) + 3) & ~3;
+    const int wave_packed = (ring_packed * L.slot_f + ring_packed * M + 4 * ring_packed + 3) & ~3;
+    if ((size_t)(4 * wave_packed + psi_packed) * 4 <= 80 * 1024) {
+        L.pad = 0;
         L.stride = M;
         L.ring = ring_packed;
+        L.psi_f = psi_packed;
+        L.wave_f = wave_packed;
+        L.waves = 4;
     } else {
+        L.pad = 1;
         L.stride = (M + 63) / 64 * 64;
         L.ring = 1;
+        L.psi_f = 0;
+        L.wave_f = (L.slot_f + 4 + 3) & ~3;
+        // the workgroup size that fits the most waves per CU (waves never
+        // synchronise in this layout, so one-wave workgroups lose nothing)
+        L.waves = 1;
+        int best = 0;
+        for (int w = 4; w >= 1; w >>= 1) {
+            const size_t bytes = (size_t)w * L.wave_f * 4;
+            const int per_cu = bytes <= 160 * 1024 ? (int)(160 * 1024 / bytes) * w : 0;
+            if (per_cu > best) {
+                best = per_cu;
+                L.waves = w;
+            }
+        }
     }
-    L.wave_f = wave_floats(L.ring);
-    L.waves = 4;
     while (L.waves > 1 && (size_t)(L.waves * L.wave_f + L.psi_f) * 4 > 160 * 1024) --L.waves;
     return L;
 }
@@ -371,9 +422,9 @@ size_t ksg_lds_bytes(int M, int pw) {
     return ((size_t)L.waves * L.wave_f + L.psi_f) * sizeof(float);
 }
 
-template <int KP, int P2>
+template <int KP, int P2, bool PAD>
 static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
-    const void* fn = (const void*)ksg_kernel<KP, P2>;
+    const void* fn = (const void*)ksg_kernel<KP, P2, PAD>;
     static bool attr = false;
     if (!attr) {
         CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -397,18 +448,19 @@ static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int 
     const int64_t min_blocks = (n_total + L.waves - 1) / L.waves;  // at least one pair per wave
     if (blocks > min_blocks) blocks = min_blocks;
     const int64_t n_waves = blocks * L.waves;
-    ksg_kernel<KP, P2><<<dim3((unsigned)blocks), threads, lds, s>>>(a, n_total, L, n_waves);
+    ksg_kernel<KP, P2, PAD><<<dim3((unsigned)blocks), threads, lds, s>>>(a, n_total, L, n_waves);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
 
 template <int KP>
 static int launch_p2(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
+    if (L.pad) return launch_kp<KP, 0, true>(a, n_total, L, num_cus, lds, s);
     switch (L.p2) {
-        case 64: return launch_kp<KP, 64>(a, n_total, L, num_cus, lds, s);
-        case 128: return launch_kp<KP, 128>(a, n_total, L, num_cus, lds, s);
-        case 256: return launch_kp<KP, 256>(a, n_total, L, num_cus, lds, s);
-        default: return launch_kp<KP, 0>(a, n_total, L, num_cus, lds, s);
+        case 64: return launch_kp<KP, 64, false>(a, n_total, L, num_cus, lds, s);
+        case 128: return launch_kp<KP, 128, false>(a, n_total, L, num_cus, lds, s);
+        case 256: return launch_kp<KP, 256, false>(a, n_total, L, num_cus, lds, s);
+        default: return launch_kp<KP, 0, false>(a, n_total, L, num_cus, lds, s);
     }
 }
 
