@@ -571,7 +571,7 @@ def run_focus(args, torch, synth, pc):
             "autotuned": {"contraction_cfg": tuned_cfg, "contraction_ms": tuned_ms, "ksg_pairs_per_wave": tuned_pw},
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "kernel": "ksg_kernel<10, 128>",
+                     "traffic": measured_traffic(), "kernel": "ksg_kernel<10, 128, false>",
                      "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair, 1e6 pairs per launch",
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
     }
