@@ -87,12 +87,12 @@ def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
     rng = np.random.default_rng(77)
     ia = e.regions[0].global_indices(e.nx, e.ny)
     ib = e.regions[1].global_indices(e.nx, e.ny)
-    n_p = 2_000_000
+    n_p = 40_000_000  # with the KSG sample about 10 s of oracle work on 16 cores
     ps = np.stack([rng.choice(ia, n_p), rng.choice(ib, n_p)], 1).astype(np.int32)
     t0 = time.perf_counter()
     r_ref = oracle.pearson_pairs(e.data, ps)
     t_p = (time.perf_counter() - t0) / n_p
-    n_k = 20_000
+    n_k = 400_000
     ks = pairs_np[rng.choice(pairs_np.shape[0], n_k, replace=False)]
     t0 = time.perf_counter()
     mi_ref, cnt_ref = oracle.ksg_pairs(e.data, ks, 10)
