@@ -25,7 +25,9 @@
  *    handle, CORR_ENOMEM when a workspace cannot be allocated, CORR_EHIP for
  *    a failed HIP call (its message is kept in corr_last_error()).
  *    No C++ exception crosses this ABI.
- *  - One host thread at a time per corr_ctx.
+ *  - One host thread at a time per corr_ctx; separate contexts may be used
+ *    from separate threads. Calls run on the calling thread's current HIP
+ *    device, which must be the device the context was created for.
  *  - Point indices are global linear indices p = x + nx * (y + ny * z),
  *    int32. A region's local index follows the same x-fastest rule relative
  *    to its origin.

@@ -8,6 +8,10 @@
 
 #include "common.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace corr {
 
 static thread_local std::string g_last_error;
@@ -38,6 +42,33 @@ int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out
         ctx->ws_size[slot] = want;
     }
     *out = ctx->ws[slot];
+    return CORR_OK;
+}
+
+int kernel_setup(const void* fn, size_t lds, int threads, int* per_cu) {
+    struct Key {
+        int device;
+        const void* fn;
+        size_t lds;
+        int threads;
+        bool operator<(const Key& o) const {
+            return std::tie(device, fn, lds, threads) < std::tie(o.device, o.fn, o.lds, o.threads);
+        }
+    };
+    static std::mutex mu;
+    static std::map<Key, int> done;
+    int dev = 0;
+    CORR_HIP(hipGetDevice(&dev));
+    const Key key{dev, fn, lds, threads};
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = done.find(key);
+    if (it == done.end()) {
+        if (lds > 64 * 1024) CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int n = 0;
+        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds));
+        it = done.emplace(key, n < 1 ? 1 : n).first;
+    }
+    if (per_cu) *per_cu = it->second;
     return CORR_OK;
 }
 

@@ -195,6 +195,12 @@ size_t sample_boxes_bytes(int32_t n_pairs);
 void fill_sample_boxes(void* host, const corr_region* regions, const int32_t* region_pairs, int32_t n_pairs,
                        const corr_field& A, const corr_field& B);
 
+// Per-device kernel set-up, done once per (device, kernel, LDS bytes, block
+// size) under a lock: raises the kernel's dynamic-LDS limit to `lds` and
+// returns the resident workgroups per CU (>= 1) in *per_cu (may be NULL).
+// Safe to call from several host threads (api.hip).
+int kernel_setup(const void* fn, size_t lds, int threads, int* per_cu);
+
 // small utility kernels (api.hip)
 int launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 

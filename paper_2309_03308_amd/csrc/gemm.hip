@@ -280,12 +280,8 @@ static int launch_p(const GemmArgs& g, int num_cus, hipStream_t s) {
     int64_t grid = (int64_t)num_cus * 2;
     if (grid > n_tiles) grid = n_tiles;
     const size_t lds = 2 * (size_t)T::STAGE;
-    static bool attr_set = false;
-    if (!attr_set) {
-        CORR_HIP(hipFuncSetAttribute((const void*)gemm_max_kernel<PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds));
-        attr_set = true;
-    }
+    int rc = kernel_setup((const void*)gemm_max_kernel<PREC>, lds, G_THREADS, nullptr);
+    if (rc) return rc;
     gemm_max_kernel<PREC><<<dim3((unsigned)grid), G_THREADS, lds, s>>>(g, n_ti, n_tj);
     CORR_LAUNCH_CHECK();
     return CORR_OK;

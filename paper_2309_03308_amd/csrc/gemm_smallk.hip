@@ -27,6 +27,8 @@
 // sign).
 #include "common.h"
 
+#include <atomic>
+
 namespace corr {
 
 typedef _Float16 sk_h8 __attribute__((ext_vector_type(8)));
@@ -415,13 +417,9 @@ static int launch_sk_t(const GemmArgs& g, int num_cus, hipStream_t s, bool query
         }
         return attr.localSizeBytes == 0 ? CORR_OK : CORR_EUNSUPPORTED;
     }
-    static int per_cu = 0;
-    if (per_cu == 0) {
-        CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        int nb = 0;
-        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds));
-        per_cu = nb < 1 ? 1 : nb;
-    }
+    int per_cu = 1;
+    const int rc = kernel_setup(fn, lds, 256, &per_cu);
+    if (rc) return rc;
     const int n_tj = (int)(g.nb_pad / BN);
     const int64_t n_ablk = g.na_pad / (32 * WM);
     // XCD rectangles: split A so that each part's rows (all parts of the
@@ -503,15 +501,19 @@ bool smallk_config_ok(int prec, int cfg, int K) {
     if ((size_t)parts * kSkCfgs[cfg].bn * (K * es + 16) > 160 * 1024) return false;  // B tile must fit LDS
     const int ki = K == 64 ? 0 : (K == 112 ? 1 : (K == 128 ? 2 : -1));
     if (ki < 0) return false;
-    static signed char cache[5][kNumSkCfgs][3] = {};
-    signed char& c = cache[prec][cfg][ki];
-    if (c == 0) {
+    // 0 = not queried yet, 1 = usable, -1 = not; the query is idempotent, so
+    // concurrent first calls at worst repeat it
+    static std::atomic<signed char> cache[5][kNumSkCfgs][3] = {};
+    std::atomic<signed char>& c = cache[prec][cfg][ki];
+    signed char v = c.load(std::memory_order_relaxed);
+    if (v == 0) {
         GemmArgs g{};
         g.prec = prec;
         g.K = K;
-        c = sk_dispatch(g, cfg, 0, nullptr, true) == CORR_OK ? 1 : -1;
+        v = sk_dispatch(g, cfg, 0, nullptr, true) == CORR_OK ? 1 : -1;
+        c.store(v, std::memory_order_relaxed);
     }
-    return c > 0;
+    return v > 0;
 }
 
 int launch_gemm_smallk(const GemmArgs& g, int cfg, int num_cus, hipStream_t s) {

@@ -425,23 +425,10 @@ size_t ksg_lds_bytes(int M, int pw) {
 template <int KP, int P2, bool PAD>
 static int launch_kp(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int num_cus, size_t lds, hipStream_t s) {
     const void* fn = (const void*)ksg_kernel<KP, P2, PAD>;
-    static bool attr = false;
-    if (!attr) {
-        CORR_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr = true;
-    }
     const int threads = 64 * L.waves;
-    static size_t cached_lds = 0;
-    static int cached_threads = 0, cached_per_cu = 0;
-    if (lds != cached_lds || threads != cached_threads) {
-        int n = 0;
-        CORR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds));
-        cached_lds = lds;
-        cached_threads = threads;
-        cached_per_cu = n;
-    }
-    int per_cu = cached_per_cu;
-    if (per_cu < 1) per_cu = 1;
+    int per_cu = 1;
+    const int rc = kernel_setup(fn, lds, threads, &per_cu);
+    if (rc) return rc;
     if (a.pw > 0 && a.pw < per_cu) per_cu = a.pw;
     // a resident grid: every wave's pair range starts at once
     int64_t blocks = (int64_t)num_cus * per_cu;

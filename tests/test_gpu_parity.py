@@ -339,3 +339,33 @@ def test_determinism(ctx, pc, torch, cfg2):
     m1 = ctx.corr_ksg_mi_pairs(f, pairs).cpu().numpy()
     m2 = ctx.corr_ksg_mi_pairs(f, pairs).cpu().numpy()
     assert np.array_equal(m1, m2)
+
+
+def test_contexts_on_two_threads(pc, torch, cfg1):
+    # separate contexts may run from separate host threads (per-device kernel
+    # set-up happens once under a lock); results equal the serial ones
+    import concurrent.futures
+    f = _field(pc, torch, cfg1)
+    ra, rb = [pc.region(*r.as_tuple()) for r in cfg1.regions]
+    rng = np.random.default_rng(12)
+    pairs = dev(torch, rng.integers(0, cfg1.P, (20000, 2)).astype(np.int32))
+
+    def work(_):
+        c = pc.Context(0)
+        try:
+            out = []
+            for _ in range(3):
+                mi = c.corr_ksg_mi_pairs(f, pairs, k=7).cpu().numpy()
+                rm = c.corr_region_max(f, ra, rb, "pearson", "f16")
+                out.append((mi, rm))
+            torch.cuda.synchronize()
+            return out
+        finally:
+            c.close()
+
+    serial = work(0)
+    with concurrent.futures.ThreadPoolExecutor(2) as ex:
+        results = list(ex.map(work, range(2)))
+    for res in results:
+        for (mi, rm), (mi0, rm0) in zip(res, serial):
+            assert np.array_equal(mi, mi0) and rm == rm0
