@@ -58,3 +58,27 @@ def mean_deviation(max_initial, max_level):
     keep = m1 != 0
     rel = float(np.mean(np.abs(mf[keep] - m1[keep]) / np.abs(m1[keep]))) if keep.any() else 0.0
     return rel, float(np.mean(np.abs(mf - m1)))
+
+
+def split_region(region, splits):
+    """Sub-bricks of a brick (x0, y0, z0, dx, dy, dz) split into splits = (sx, sy, sz)
+    parts per axis, as evenly as possible with the first parts one cell
+    larger; listed x-fastest. Brick refinement (Sec. 4) halves each axis,
+    splits = (2, 2, 2)."""
+    x0, y0, z0, dx, dy, dz = region
+    axes = []
+    for o, d, s in ((x0, dx, splits[0]), (y0, dy, splits[1]), (z0, dz, splits[2])):
+        if not (1 <= s <= d):
+            raise ValueError("split count outside [1, extent]")
+        parts, start = [], o
+        for i in range(s):
+            n = d // s + (1 if i < d % s else 0)
+            parts.append((start, n))
+            start += n
+        axes.append(parts)
+    out = []
+    for (z, nz) in axes[2]:
+        for (y, ny) in axes[1]:
+            for (x, nx) in axes[0]:
+                out.append((x, y, z, nx, ny, nz))
+    return out

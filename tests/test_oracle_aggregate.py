@@ -100,3 +100,30 @@ def test_region_at_level():
 def test_mean_deviation():
     rel, ab = AG.mean_deviation([0.5, 1.0, 0.0], [0.45, 1.1, 0.2])
     assert abs(rel - 0.1) < 1e-12 and abs(ab - (0.05 + 0.1 + 0.2) / 3) < 1e-12
+
+
+@pytest.mark.parametrize("region,splits", [((3, 1, 0, 32, 32, 20), (2, 2, 2)), ((0, 0, 0, 7, 5, 3), (3, 2, 3)),
+                                           ((2, 2, 2, 5, 1, 4), (5, 1, 2))])
+def test_split_region_partitions_the_brick(region, splits):
+    subs = AG.split_region(region, splits)
+    assert len(subs) == splits[0] * splits[1] * splits[2]
+    x0, y0, z0, dx, dy, dz = region
+    cover = np.zeros((dz, dy, dx), int)
+    for (x, y, z, nx, ny, nz) in subs:
+        cover[z - z0:z - z0 + nz, y - y0:y - y0 + ny, x - x0:x - x0 + nx] += 1
+    assert np.all(cover == 1)  # disjoint and covering
+    for j, (d, s) in enumerate(zip((dx, dy, dz), splits)):
+        sizes = sorted({sb[3 + j] for sb in subs})
+        assert sizes[-1] - sizes[0] <= 1 and sum(sorted({(sb[j], sb[3 + j]) for sb in subs})[i][1]
+                                                  for i in range(s)) == d
+    # x-fastest: the second sub-brick moves along x when x is split
+    if splits[0] > 1:
+        assert subs[1][0] > subs[0][0] and subs[1][1:3] == subs[0][1:3]
+    with pytest.raises(ValueError):
+        AG.split_region((0, 0, 0, 2, 2, 2), (3, 1, 1))
+
+
+def test_split_region_first_parts_larger():
+    assert AG.split_region((0, 0, 0, 7, 1, 1), (3, 1, 1)) == [(0, 0, 0, 3, 1, 1), (3, 0, 0, 2, 1, 1), (5, 0, 0, 2, 1, 1)]
+    assert AG.split_region((4, 0, 0, 2, 2, 1), (2, 2, 1)) == [(4, 0, 0, 1, 1, 1), (5, 0, 0, 1, 1, 1),
+                                                               (4, 1, 0, 1, 1, 1), (5, 1, 0, 1, 1, 1)]
