@@ -207,6 +207,24 @@ int corr_tune_save(corr_ctx* ctx, const char* path);
 int corr_tune_load(corr_ctx* ctx, const char* path);
 
 /*
+ * Sub-brick maxima: one level of brick refinement of a pair (Sec. 4, the
+ * focus view refines a selected brick pair). Brick ra is split into
+ * splits_a[0] x splits_a[1] x splits_a[2] sub-bricks and rb into splits_b
+ * likewise (each axis as evenly as possible, the first parts one cell
+ * larger), and for every (sub-brick i of ra, sub-brick j of rb) the exhaustive
+ * Pearson maximum of |r| is computed exactly as corr_region_max does it
+ * (same precision modes, the same exclusion of a point paired with itself
+ * within one field, the same argmax rule). Both fields are standardised once.
+ *   splits_a, splits_b: HOST int32[3], each in [1, the axis extent].
+ *   out: HOST corr_max[n_a * n_b], out[i * n_b + j], sub-bricks numbered
+ *        x-fastest (x, then y, then z).
+ * CORR_EINVAL for bad splits or regions; synchronises `stream`.
+ */
+int corr_region_submax(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const int32_t* splits_a,
+                       const corr_field* B, const corr_region* rb, const int32_t* splits_b, int prec,
+                       corr_max* out, corr_stream_t stream);
+
+/*
  * Samples of brick pairs (Sec. 3.1: random or quasi-random sampling of the
  * 6-D box x, y, z in brick A and x, y, z in brick B). For region pair p
  * (regions[region_pairs[2p]], regions[region_pairs[2p+1]]) and sample

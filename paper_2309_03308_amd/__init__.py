@@ -168,6 +168,21 @@ class Context:
         return dict(value=out.value, signed_value=out.signed_value, pa=out.pa, pb=out.pb,
                     n_evaluated=out.n_evaluated)
 
+    def corr_region_submax(self, A: Field, ra: corr_region, rb: corr_region, splits_a=(2, 2, 2), splits_b=(2, 2, 2),
+                           prec="f16", B: Field = None, stream=None):
+        """Exhaustive Pearson maxima of every (sub-brick of ra, sub-brick of rb):
+        a list of lists of corr_region_max-style dicts, [i][j], sub-bricks x-fastest."""
+        B = A if B is None else B
+        sa = (ctypes.c_int32 * 3)(*[int(v) for v in splits_a])
+        sb = (ctypes.c_int32 * 3)(*[int(v) for v in splits_b])
+        na, nb = int(np.prod(splits_a)), int(np.prod(splits_b))
+        res = (corr_max * max(1, na * nb))()  # the library rejects bad splits before writing
+        _lib.check(self.L.corr_region_submax(self.h, ctypes.byref(A.c), ctypes.byref(ra), ctypes.cast(sa, ctypes.c_void_p),
+                                             ctypes.byref(B.c), ctypes.byref(rb), ctypes.cast(sb, ctypes.c_void_p),
+                                             PREC[prec], ctypes.cast(res, ctypes.c_void_p), _stream_ptr(stream)))
+        return [[dict(value=r.value, signed_value=r.signed_value, pa=r.pa, pb=r.pb, n_evaluated=r.n_evaluated)
+                 for r in res[i * nb:(i + 1) * nb]] for i in range(na)]
+
     # ------------------------------------------------------------------ sampling
     @staticmethod
     def _region_arrays(regions, region_pairs):

@@ -92,6 +92,8 @@ SIGNATURES = {
     "corr_sampled_max": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I32, _P, _I32, _I,
                               _I, _I32, _I, _I32, ctypes.c_uint64, _P, _P]),
     "corr_choose_strategy": (_I, [_I64, _I64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_I32)]),
+    "corr_region_submax": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _P,
+                                ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _P, _I, _P, _P]),
     "prop_mlp_create": (_I, [_P, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "prop_mlp_num_params": (_I, [_P, ctypes.POINTER(_I64)]),
     "prop_mlp_get_params": (_I, [_P, _P]),

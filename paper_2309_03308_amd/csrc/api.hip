@@ -876,4 +876,146 @@ int corr_choose_strategy(int64_t na, int64_t nb, double pairs_per_s, double budg
     return CORR_OK;
 }
 
+// ---- sub-brick maxima (one refinement level of a brick pair) ---------------
+static int split_box(const corr_region& r, const int32_t* splits, const corr_field& f, std::vector<Box>& out) {
+    const int32_t o[3] = {r.x0, r.y0, r.z0}, d[3] = {r.dx, r.dy, r.dz};
+    std::vector<int32_t> st[3], len[3];
+    for (int a = 0; a < 3; ++a) {
+        if (splits[a] < 1 || splits[a] > d[a]) return fail(CORR_EINVAL, "split count outside [1, axis extent]");
+        int32_t start = o[a];
+        for (int i = 0; i < splits[a]; ++i) {
+            const int32_t n = d[a] / splits[a] + (i < d[a] % splits[a] ? 1 : 0);
+            st[a].push_back(start);
+            len[a].push_back(n);
+            start += n;
+        }
+    }
+    out.clear();
+    for (size_t z = 0; z < st[2].size(); ++z)
+        for (size_t y = 0; y < st[1].size(); ++y)
+            for (size_t x = 0; x < st[0].size(); ++x)
+                out.push_back(Box{st[0][x], st[1][y], st[2][z], len[0][x], len[1][y], len[2][z], f.nx, f.ny});
+    return CORR_OK;
+}
+
+int corr_region_submax(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const int32_t* splits_a,
+                       const corr_field* B, const corr_region* rb, const int32_t* splits_b, int prec,
+                       corr_max* out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if ((rc = check_field(B, "B"))) return rc;
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if ((rc = check_region(ra, *A, "ra"))) return rc;
+    if ((rc = check_region(rb, *B, "rb"))) return rc;
+    if (!splits_a || !splits_b || !out) return fail(CORR_EINVAL, "null splits or output");
+    if (prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3) return fail(CORR_EUNSUPPORTED, "unknown precision");
+    std::vector<Box> sa, sb;
+    if ((rc = split_box(*ra, splits_a, *A, sa))) return rc;
+    if ((rc = split_box(*rb, splits_b, *B, sb))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool sf = same_field(*A, *B);
+    const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
+    const int fmt = zfmt_for_prec(prec);
+    const bool small = A->M <= 128;
+    int64_t K, row_pad, col_pad;
+    int cfg = -1;
+    if (small) {
+        K = smallk_pad_K(A->M);
+        cfg = default_smallk_cfg(prec, (int)K);
+        row_pad = smallk_row_pad(cfg);
+        col_pad = smallk_col_pad(cfg);
+    } else {
+        K = round_up(A->M, gemm_k_pad(prec));
+        row_pad = gemm_row_pad();
+        col_pad = gemm_col_pad();
+    }
+    const size_t es = prec == CORR_PREC_F32 ? 4 : 2;
+    const bool split = prec_split(prec);
+    // rows of every sub-brick, each block padded for the contraction
+    auto layout = [&](const std::vector<Box>& boxes, int64_t pad, std::vector<int64_t>& off, int64_t& total,
+                      int64_t& largest) {
+        off.clear();
+        total = 0;
+        largest = 0;
+        for (const Box& b : boxes) {
+            off.push_back(total);
+            total += round_up(b.count(), pad);
+            largest = std::max(largest, b.count());
+        }
+    };
+    std::vector<int64_t> offa, offb;
+    int64_t tot_a, tot_b, big_a, big_b;
+    layout(sa, row_pad, offa, tot_a, big_a);
+    layout(sb, col_pad, offb, tot_b, big_b);
+    void *ah = nullptr, *al = nullptr, *bh = nullptr, *bl = nullptr, *sta = nullptr, *keys = nullptr;
+    if ((rc = ws_get(ctx, WS_SUB_AH, es * (size_t)(tot_a * K), s, &ah))) return rc;
+    if ((rc = ws_get(ctx, WS_SUB_BH, es * (size_t)(tot_b * K), s, &bh))) return rc;
+    if (split) {
+        if ((rc = ws_get(ctx, WS_SUB_AL, es * (size_t)(tot_a * K), s, &al))) return rc;
+        if ((rc = ws_get(ctx, WS_SUB_BL, es * (size_t)(tot_b * K), s, &bl))) return rc;
+    }
+    if ((rc = ws_get(ctx, WS_STATS_A, sizeof(float) * 4 * (size_t)std::max(big_a, big_b), s, &sta))) return rc;
+    const size_t n_out = sa.size() * sb.size();
+    if ((rc = ws_get(ctx, WS_SUB_KEYS, sizeof(unsigned long long) * 2 * n_out, s, &keys))) return rc;
+    if ((rc = launch_fill_u64((unsigned long long*)keys, 2 * (int64_t)n_out, 0ull, s))) return rc;
+    auto stage = [&](const corr_field& f, const std::vector<Box>& boxes, const std::vector<int64_t>& off, int64_t pad,
+                     void* hi, void* lo) {
+        for (size_t i = 0; i < boxes.size(); ++i) {
+            const int64_t n = boxes[i].count();
+            Stats st = stats_view((float*)sta, n);
+            int r = launch_stats(f, boxes[i], acc64, st, s);
+            if (r) return r;
+            unsigned char* h = (unsigned char*)hi + es * (size_t)(off[i] * K);
+            unsigned char* l = lo ? (unsigned char*)lo + es * (size_t)(off[i] * K) : nullptr;
+            r = launch_transpose(f, boxes[i], st, fmt, h, l, round_up(n, pad), K, s);
+            if (r) return r;
+        }
+        return (int)CORR_OK;
+    };
+    if ((rc = stage(*A, sa, offa, row_pad, ah, al))) return rc;
+    if ((rc = stage(*B, sb, offb, col_pad, bh, bl))) return rc;
+    // self columns of overlapping sub-brick pairs (one field only)
+    void* selfbuf = nullptr;
+    if (sf && boxes_overlap(region_box(*ra, *A), region_box(*rb, *B)))
+        if ((rc = ws_get(ctx, WS_MISC, sizeof(int32_t) * (size_t)big_a, s, &selfbuf))) return rc;
+    for (size_t i = 0; i < sa.size(); ++i) {
+        for (size_t j = 0; j < sb.size(); ++j) {
+            const int64_t na = sa[i].count(), nb = sb[j].count();
+            GemmArgs g{};
+            g.prec = prec;
+            g.a_hi = (unsigned char*)ah + es * (size_t)(offa[i] * K);
+            g.a_lo = al ? (unsigned char*)al + es * (size_t)(offa[i] * K) : nullptr;
+            g.b_hi = (unsigned char*)bh + es * (size_t)(offb[j] * K);
+            g.b_lo = bl ? (unsigned char*)bl + es * (size_t)(offb[j] * K) : nullptr;
+            g.K = K;
+            g.na = na;
+            g.nb = nb;
+            g.na_pad = round_up(na, row_pad);
+            g.nb_pad = round_up(nb, col_pad);
+            g.self_col = nullptr;
+            if (selfbuf && boxes_overlap(sa[i], sb[j])) {
+                // the buffer is reused by the next overlapping pair only after
+                // this pair's contraction (stream order)
+                self_col_kernel<<<dim3((unsigned)((na + 255) / 256)), 256, 0, s>>>(sa[i], sb[j], (int32_t*)selfbuf);
+                CORR_LAUNCH_CHECK();
+                g.self_col = (const int32_t*)selfbuf;
+            }
+            g.key = (unsigned long long*)keys + 2 * (i * sb.size() + j);
+            rc = small ? launch_gemm_smallk(g, cfg, ctx->num_cus, s) : launch_gemm_max(g, ctx->num_cus, s);
+            if (rc) return rc;
+        }
+    }
+    std::vector<unsigned long long> hk(2 * n_out);
+    CORR_HIP(hipMemcpyAsync(hk.data(), keys, sizeof(unsigned long long) * hk.size(), hipMemcpyDeviceToHost, s));
+    CORR_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < sa.size(); ++i)
+        for (size_t j = 0; j < sb.size(); ++j) {
+            corr_max& o = out[i * sb.size() + j];
+            decode_key(hk[2 * (i * sb.size() + j)], sa[i], sb[j], true, &o);
+            o.n_evaluated = sa[i].count() * sb[j].count() - (sf ? overlap_count(sa[i], sb[j]) : 0);
+        }
+    return CORR_OK;
+}
+
 }  // extern "C"

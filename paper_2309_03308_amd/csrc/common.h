@@ -54,7 +54,8 @@ struct Box {
 // ---- workspace --------------------------------------------------------------
 enum WsSlot {
     WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
-    WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_SAMPLES, WS_SVALUES, WS_SBOXES, WS_COUNT
+    WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_SAMPLES, WS_SVALUES, WS_SBOXES,
+    WS_SUB_AH, WS_SUB_AL, WS_SUB_BH, WS_SUB_BL, WS_SUB_KEYS, WS_COUNT
 };
 
 }  // namespace corr
