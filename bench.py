@@ -35,6 +35,7 @@ N_KSG = 1_000_000
 M = 100
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
 MFMA_F16_PEAK = 2.5e15
+LDS_BYTES_PER_S = 256 * 128 * 2.4e9  # CUs x LDS bytes per clock x clock
 HBM_PEAK = 8.0e12
 
 
@@ -48,6 +49,21 @@ def source_hash(path):
     import hashlib
     with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_value(name, summary=TRAFFIC_FILE, source=KSG_SOURCE, key="ksg_source_sha256"):
+    """A figure of a committed counter summary, or None when missing or stale."""
+    try:
+        vals = {}
+        for line in open(summary):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        if vals.get(key) != source_hash(source):
+            return None
+        return float(vals[name])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def measured_traffic(summary=TRAFFIC_FILE, source=KSG_SOURCE, key="ksg_source_sha256"):
@@ -98,6 +114,19 @@ def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
     mi_ref, cnt_ref = oracle.ksg_pairs(e.data, ks, 10)
     t_k = (time.perf_counter() - t0) / n_k
     t_step = N_PEARSON * t_p + N_KSG * t_k
+    # the same oracle on one core (smaller sample of each kind)
+    cores = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.pearson_pairs(e.data, ps[:1_000_000])
+        t_p1 = (time.perf_counter() - t0) / 1_000_000
+        t0 = time.perf_counter()
+        oracle.ksg_pairs(e.data, ks[:10_000], 10, want_counts=False)
+        t_k1 = (time.perf_counter() - t0) / 10_000
+    finally:
+        oracle.set_num_threads(cores)
+    t_step1 = N_PEARSON * t_p1 + N_KSG * t_k1
     # errors of the GPU path on the same sample
     r_gpu = ctx.corr_pearson_pairs(f, torch.from_numpy(ps).cuda(), "f16").cpu().numpy()
     mi_gpu, cnt_gpu = ctx.corr_ksg_mi_pairs(f, torch.from_numpy(ks).cuda(), k=10, counts=True)
@@ -117,6 +146,8 @@ def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
                    f"{n_k} of the 1e6 sampled pairs ({t_k * 1e6:.1f} us/pair), extrapolated to one step "
                    f"(4.19e8 Pearson + 1e6 KSG pairs)"),
         "cpu_model": cpu_model(),
+        "single_core_value": (N_PEARSON + N_KSG) / t_step1,
+        "single_core_sample": f"1e6 Pearson pairs ({t_p1 * 1e9:.1f} ns/pair), 1e4 KSG pairs ({t_k1 * 1e6:.1f} us/pair)",
     }, err
 
 
@@ -568,7 +599,11 @@ def run_focus(args, torch, synth, pc):
             "ksg_pairs_per_s_kernel": N_KSG / (ksg_ms / 1e3),
             "pearson_max": res["pearson"]["value"],
             "ksg_max": res["ksg"]["value"],
-            "autotuned": {"contraction_cfg": tuned_cfg, "contraction_ms": tuned_ms, "ksg_pairs_per_wave": tuned_pw},
+            "autotuned": {"contraction_cfg": tuned_cfg, "contraction_ms": tuned_ms, "ksg_workgroups_per_cu": tuned_pw},
+            # what binds KSG: VALU issue (counters) versus the LDS stream of
+            # neighbour samples (8 B per distance) against 256 CU x 128 B/clk x 2.4 GHz
+            "ksg_valu_busy_counters": measured_value("valu_busy"),
+            "ksg_lds_frac": N_KSG * M * (M - 1) * 8.0 / (ksg_ms / 1e3) / LDS_BYTES_PER_S,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
                      "traffic": measured_traffic(), "kernel": "ksg_kernel<10, 128, false>",

@@ -58,6 +58,7 @@ def lib():
         L.orc_argmax_pairs.restype = I64
         L.orc_pearson_region_max.argtypes = [P, I64, P, I64, P, I64, P, I64, I, I, P, P, P, P, P]
         L.orc_num_threads.restype = I
+        L.orc_set_num_threads.argtypes = [I]
         _lib = L
     return _lib
 
@@ -75,6 +76,11 @@ def _f32(data):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the C oracle (timing only; results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def digamma_int(n: int) -> float:

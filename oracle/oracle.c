@@ -272,3 +272,4 @@ void orc_pearson_region_max(const float* xa, int64_t sa, const int32_t* pa, int6
 /* Threads an OpenMP parallel region of the oracle uses. */
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
