@@ -913,6 +913,8 @@ int corr_region_submax(corr_ctx* ctx, const corr_field* A, const corr_region* ra
     std::vector<Box> sa, sb;
     if ((rc = split_box(*ra, splits_a, *A, sa))) return rc;
     if ((rc = split_box(*rb, splits_b, *B, sb))) return rc;
+    if (sa[0].count() * sb[0].count() >= (int64_t(1) << 31))  // the first sub-bricks are the largest
+        return fail(CORR_EUNSUPPORTED, "a sub-brick pair has 2^31 or more point pairs");
     hipStream_t s = (hipStream_t)stream;
     const bool sf = same_field(*A, *B);
     const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
