@@ -649,6 +649,7 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     a.mi_out = mi_out;
     a.counts_out = counts_out;
     a.key = nullptr;
+    a.work = ctx->keys + 8;
     a.ba = ba;
     a.bb = bb;
     a.whole_a = 1;
@@ -744,6 +745,7 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     a.k = k;
     a.psi = ctx->psi;
     a.key = ctx->keys;
+    a.work = ctx->keys + 8;
     a.ba = ba;
     a.bb = bb;
     a.whole_a = (ba.count() == (int64_t)A->nx * A->ny * A->nz) ? 1 : 0;

@@ -146,7 +146,8 @@ struct KsgArgs {
     int same_field;        // skip pA == pB
     const float* sa;       // rows of za / zb sorted ascending, row stride ksg_p2(M), +inf padded
     const float* sb;
-    int pw;                // pairs per wave chunk (<= 0: default)
+    int pw;                // workgroups per CU cap of the resident grid (<= 0: the occupancy limit)
+    unsigned long long* work;  // device word the waves take pair chunks from (zeroed by launch_ksg)
     int whole_a, whole_b;  // box covers the whole grid: local index = global index
 };
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s);

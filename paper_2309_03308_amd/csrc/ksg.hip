@@ -126,29 +126,66 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
     }
 
     const int M = a.M, k = a.k, S = L.stride, R = L.ring;
-    const int64_t gw = (int64_t)blockIdx.x * L.waves + wave;
-    const int64_t p_begin = n_total * gw / n_waves, p_end = n_total * (gw + 1) / n_waves;
-    const int np = (int)(p_end - p_begin);
-    if (np <= 0) return;
     float* wb = lds_f + L.psi_f + wave * L.wave_f;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(wb + R * L.slot_f);  // [R][M] packed n_x | n_y << 16
-    int* info = reinterpret_cast<int*>(cnt + (PAD ? 0 : R * M));     // [R][4]
+    int* info = reinterpret_cast<int*>(cnt + (PAD ? 0 : R * M));     // [R][8]: la, lb, state, in_max, pair
     double lacc = 0.0;                                               // PAD: this lane's digamma sum
     const int64_t nb = a.bb.count();
     const float inf = __builtin_inff();
     unsigned long long best = 0;
     uint32_t n_in_max = 0;
 
+    // The wave's pairs: a sequence of chunks. Padded layout (expensive
+    // pairs): chunks taken from a device-wide counter with guided sizes (a
+    // share of what is left, down to one pair near the end), so waves that
+    // start late or share a CU with more waves only cost a short tail. Packed
+    // layout: one contiguous range per wave. Local pair s of the sequence is
+    // global pair cbase + (s - cstart) of the chunk being staged; a staged
+    // pair keeps its global index in `info`.
     // per lane: local pair q, sample i, ring slot r of item U + lane
     int q = lane / S, i = lane - (lane / S) * S, r = q % R;
-    int staged = 0, done = 0;
-    const int64_t n_items = (int64_t)np * S;
-    for (int64_t U = 0; U < n_items; U += 64) {
+    int staged = 0, done = 0, np_end = 0x7fffffff;
+    int64_t cbase = 0;
+    int cstart = 0, cend = 0;
+    for (;;) {
         // ---- stage every pair this trip reaches (uniform loop)
-        const int need = min(__builtin_amdgcn_readlane(q, 63), np - 1);
-        for (; staged <= need; ++staged) {
+        const int need = __builtin_amdgcn_readlane(q, 63);
+        for (; staged <= need && staged < np_end; ++staged) {
+            if (staged == cend) {  // the current chunk is used up: take the next one
+                if constexpr (PAD) {
+                    unsigned long long got = 0;
+                    if (lane == 0) {
+                        const unsigned long long seen =
+                            __hip_atomic_load(a.work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const long long left = n_total - (long long)seen;
+                        long long want = left / (4 * n_waves);
+                        want = want < 1 ? 1 : (want > 64 ? 64 : want);
+                        got = atomicAdd(a.work, (unsigned long long)want) | ((unsigned long long)want << 48);
+                    }
+                    got = __shfl(got, 0, 64);
+                    cbase = (int64_t)(got & 0xffffffffffffull);
+                    cend = staged + (int)(got >> 48);
+                } else {
+                    // cheap pairs: one static range per wave (a counter shared by
+                    // every wave of the device costs more than the tail it saves)
+                    if (staged == 0) {
+                        const int64_t gw = (int64_t)blockIdx.x * L.waves + wave;
+                        cbase = n_total * gw / n_waves;
+                        cend = (int)(n_total * (gw + 1) / n_waves - cbase);
+                    }  // a later call leaves cend == staged: the range is done
+                }
+                cstart = staged;
+                if (staged >= cend) {  // an empty chunk: this wave's sequence ends here
+                    np_end = staged;
+                    break;
+                }
+            }
+            const int64_t t = cbase + (staged - cstart);
+            if (t >= n_total) {  // the work has run out: this wave's sequence ends here
+                np_end = staged;
+                break;
+            }
             const int sr = staged % R;
-            const int64_t t = p_begin + staged;
             int la = -1, lb = -1, state = 0, in_max = 0;
             bool same = false;
             if (a.pairs) {
@@ -169,10 +206,11 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
                 in_max = (a.key != nullptr) && !(a.same_field && same);
             }
             if (lane == 0) {
-                info[4 * sr] = la;
-                info[4 * sr + 1] = lb;
-                info[4 * sr + 2] = state;
-                info[4 * sr + 3] = in_max;
+                info[8 * sr] = la;
+                info[8 * sr + 1] = lb;
+                info[8 * sr + 2] = state;
+                info[8 * sr + 3] = in_max;
+                reinterpret_cast<int64_t*>(info + 8 * sr)[2] = t;
             }
             if (state == 1) {
                 float* slot = wb + sr * L.slot_f;
@@ -195,9 +233,10 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             }
         }
         wave_lds_sync();
+        if (__builtin_amdgcn_readlane(q, 0) >= np_end) break;  // every staged pair is retired
 
         // ---- one item per lane
-        const bool act = q < np && i < M;
+        const bool act = q < np_end && i < M;
         const int ic = i < M ? i : M - 1;
         const float* slot = wb + r * L.slot_f;
         const float2* row = reinterpret_cast<const float2*>(slot);
@@ -248,13 +287,16 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
         nx = nx < 0 ? 0 : nx;
         ny = ny < 0 ? 0 : ny;
         if (act) {
-            const bool eval = info[4 * r + 2] == 1;
+            const bool eval = info[8 * r + 2] == 1;
             if constexpr (PAD) {
                 if (eval) lacc += psi[nx + 1] + psi[ny + 1];
             } else {
                 cnt[r * M + i] = (uint32_t)nx | ((uint32_t)ny << 16);
             }
-            if (a.counts_out && eval) reinterpret_cast<int2*>(a.counts_out)[(p_begin + q) * M + i] = make_int2(nx, ny);
+            if (a.counts_out && eval) {
+                const int64_t tq = reinterpret_cast<const int64_t*>(info + 8 * r)[2];
+                reinterpret_cast<int2*>(a.counts_out)[tq * M + i] = make_int2(nx, ny);
+            }
         }
         wave_lds_sync();
 
@@ -265,10 +307,10 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             ++q;
             r = (r + 1 == R) ? 0 : r + 1;
         }
-        const int complete = min(__builtin_amdgcn_readlane(q, 0), np);
+        const int complete = min(__builtin_amdgcn_readlane(q, 0), min(staged, np_end));
         for (; done < complete; ++done) {
             const int dr = done % R;
-            const int state = info[4 * dr + 2];
+            const int state = info[8 * dr + 2];
             double acc = 0.0;
             if constexpr (PAD) {
                 acc = lacc;
@@ -282,14 +324,14 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             }
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            const int64_t tp = p_begin + done;
+            const int64_t tp = reinterpret_cast<const int64_t*>(info + 8 * dr)[2];
             if (lane == 0) {
                 float mi = 0.0f;
                 if (state == 1) mi = (float)(psi[M] + psi[k] - acc / (double)M);
                 if (a.mi_out) a.mi_out[tp] = mi;
-                if (info[4 * dr + 3] && state != 0) {
+                if (info[8 * dr + 3] && state != 0) {
                     const unsigned long long key =
-                        make_key(mi, (uint32_t)((int64_t)info[4 * dr] * nb + info[4 * dr + 1]), 0u);
+                        make_key(mi, (uint32_t)((int64_t)info[8 * dr] * nb + info[8 * dr + 1]), 0u);
                     best = key > best ? key : best;
                     ++n_in_max;
                 }
@@ -316,7 +358,8 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
 }
 
 // One wave per row: bitonic sort of the row's M values (padded to p2 with
-// +inf) in LDS, written to out[row * p2 ...].
+// +inf) in the wave's LDS row, written to out[row * p2 ...]. Waves sort
+// independent rows, so they order their LDS steps among their own lanes only.
 __global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict__ z, int64_t ld, int64_t nrows, int M,
                                                         int p2, float* __restrict__ out) {
     extern __shared__ float srt[];
@@ -324,9 +367,9 @@ __global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict_
     float* s = srt + wave * p2;
     for (int64_t r0 = (int64_t)blockIdx.x * 4; r0 < nrows; r0 += (int64_t)gridDim.x * 4) {
         const int64_t r = r0 + wave;
-        const bool act = r < nrows;
-        for (int j = lane; j < p2; j += 64) s[j] = (act && j < M) ? z[r * ld + j] : __builtin_inff();
-        __syncthreads();
+        if (r >= nrows) break;  // wave-uniform; no workgroup barrier follows
+        for (int j = lane; j < p2; j += 64) s[j] = j < M ? z[r * ld + j] : __builtin_inff();
+        wave_lds_sync();
         for (int size = 2; size <= p2; size <<= 1) {
             for (int stride = size >> 1; stride >= 1; stride >>= 1) {
                 for (int e = lane; e < p2 / 2; e += 64) {
@@ -339,12 +382,11 @@ __global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict_
                         s[hi] = x;
                     }
                 }
-                __syncthreads();
+                wave_lds_sync();
             }
         }
-        if (act)
-            for (int j = lane; j < p2; j += 64) out[r * p2 + j] = s[j];
-        __syncthreads();
+        for (int j = lane; j < p2; j += 64) out[r * p2 + j] = s[j];
+        wave_lds_sync();  // the row is rewritten by the next trip
     }
 }
 
@@ -385,7 +427,7 @@ static KsgLayout ksg_layout(int M) {
     // other in LDS with room for two workgroups, else padded items
     const int ring_packed = (63 + M - 1) / M + 1;
     const int psi_packed = (2 * (M + 1) + 3) & ~3;
-    const int wave_packed = (ring_packed * L.slot_f + ring_packed * M + 4 * ring_packed + 3) & ~3;
+    const int wave_packed = (ring_packed * L.slot_f + ring_packed * M + 8 * ring_packed + 3) & ~3;
     if ((size_t)(4 * wave_packed + psi_packed) * 4 <= 80 * 1024) {
         L.pad = 0;
         L.stride = M;
@@ -398,7 +440,7 @@ static KsgLayout ksg_layout(int M) {
         L.stride = (M + 63) / 64 * 64;
         L.ring = 1;
         L.psi_f = 0;
-        L.wave_f = (L.slot_f + 4 + 3) & ~3;
+        L.wave_f = (L.slot_f + 8 + 3) & ~3;
         // the workgroup size that fits the most waves per CU (waves never
         // synchronise in this layout, so one-wave workgroups lose nothing)
         L.waves = 1;
@@ -457,6 +499,9 @@ int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
     const KsgLayout L = ksg_layout(a.M);
     const size_t lds = ksg_lds_bytes(a.M, a.pw);
     if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
+    if (!a.work) return fail(CORR_EINVAL, "KSG: no work counter");
+    int rc = launch_fill_u64(a.work, 1, 0ull, s);
+    if (rc) return rc;
     // selection width: the smallest instantiated KP >= k
     const int k = a.k;
     if (k == 10) return launch_p2<10>(a, n_total, L, num_cus, lds, s);
