@@ -390,6 +390,53 @@ __global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict_
     }
 }
 
+// Register form for rows of at most 256: lane l holds elements
+// l E .. l E + E - 1 (E = P2 / 64); compare-exchange partners closer than E
+// sit in the same lane, the others E-blocks away in lane l ^ (stride / E).
+template <int P2>
+__global__ __launch_bounds__(256) void sort_rows_reg_kernel(const float* __restrict__ z, int64_t ld, int64_t nrows,
+                                                            int M, float* __restrict__ out) {
+    constexpr int E = P2 / 64;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (r >= nrows) return;
+    float v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int e = lane * E + j;
+        v[j] = e < M ? z[r * ld + e] : __builtin_inff();
+    }
+#pragma unroll
+    for (int size = 2; size <= P2; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride >= 1; stride >>= 1) {
+            if (stride < E) {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int e = lane * E + j;
+                    if ((j & stride) == 0) {
+                        const bool asc = (e & size) == 0;
+                        const float a = v[j], b = v[j | stride];
+                        v[j] = asc ? fminf(a, b) : fmaxf(a, b);
+                        v[j | stride] = asc ? fmaxf(a, b) : fminf(a, b);
+                    }
+                }
+            } else {
+                const int lx = stride / E;
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int e = lane * E + j;
+                    const float o = __shfl_xor(v[j], lx, 64);
+                    const bool lower = (e & stride) == 0, asc = (e & size) == 0;
+                    v[j] = (lower == asc) ? fminf(v[j], o) : fmaxf(v[j], o);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) out[r * P2 + lane * E + j] = v[j];
+}
+
 // Sorted-row length: a power of two with at least one +inf sentinel after
 // the M values, so a run can reach the end of the row (the branch-free
 // searches return at most p2 - 1).
@@ -402,6 +449,14 @@ int ksg_p2(int M) {
 int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* out, int num_cus, hipStream_t s) {
     if (nrows == 0) return CORR_OK;
     const int p2 = ksg_p2(M);
+    if (p2 <= 256) {  // register form, one wave per row
+        const unsigned grid = (unsigned)((nrows + 3) / 4);
+        if (p2 == 64) sort_rows_reg_kernel<64><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
+        else if (p2 == 128) sort_rows_reg_kernel<128><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
+        else sort_rows_reg_kernel<256><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
+        CORR_LAUNCH_CHECK();
+        return CORR_OK;
+    }
     int64_t blocks = (nrows + 3) / 4;
     int64_t cap = (int64_t)num_cus * 8;
     if (blocks > cap) blocks = cap;
