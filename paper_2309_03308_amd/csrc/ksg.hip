@@ -390,7 +390,7 @@ __global__ __launch_bounds__(256) void sort_rows_kernel(const float* __restrict_
     }
 }
 
-// Register form for rows of at most 256: lane l holds elements
+// Register form for rows of at most 2048: lane l holds elements
 // l E .. l E + E - 1 (E = P2 / 64); compare-exchange partners closer than E
 // sit in the same lane, the others E-blocks away in lane l ^ (stride / E).
 template <int P2>
@@ -449,11 +449,16 @@ int ksg_p2(int M) {
 int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* out, int num_cus, hipStream_t s) {
     if (nrows == 0) return CORR_OK;
     const int p2 = ksg_p2(M);
-    if (p2 <= 256) {  // register form, one wave per row
+    if (p2 <= 2048) {  // register form, one wave per row
         const unsigned grid = (unsigned)((nrows + 3) / 4);
-        if (p2 == 64) sort_rows_reg_kernel<64><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
-        else if (p2 == 128) sort_rows_reg_kernel<128><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
-        else sort_rows_reg_kernel<256><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out);
+        switch (p2) {
+            case 64: sort_rows_reg_kernel<64><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+            case 128: sort_rows_reg_kernel<128><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+            case 256: sort_rows_reg_kernel<256><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+            case 512: sort_rows_reg_kernel<512><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+            case 1024: sort_rows_reg_kernel<1024><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+            default: sort_rows_reg_kernel<2048><<<dim3(grid), 256, 0, s>>>(z, ld, nrows, M, out); break;
+        }
         CORR_LAUNCH_CHECK();
         return CORR_OK;
     }
