@@ -191,11 +191,11 @@ int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, con
                   const corr_region* rb, int prec, int reps, int* best_cfg, float* best_ms, corr_stream_t stream);
 
 /*
- * Autotuner for the KSG pair mapping (Sec. 3.2 estimator; how many pairs one
- * wave stages and spreads its (pair, sample) items over): times each
- * candidate on the given pair list (as corr_ksg_mi_pairs would run it) and
- * records the fastest for (M, k). best_pw / best_ms HOST, nullable.
- * Synchronises `stream`.
+ * Autotuner for the KSG launch (Sec. 3.2 estimator): times each candidate
+ * cap on the workgroups per CU of the resident grid (1, 2, 4, 8, 16; the
+ * kernel's occupancy limit applies on top) on the given pair list, as
+ * corr_ksg_mi_pairs would run it, and records the fastest for (M, k).
+ * best_pw (the cap) / best_ms: HOST, nullable. Synchronises `stream`.
  */
 int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, const int32_t* pairs, int64_t n,
                       int32_t k, int reps, int* best_pw, float* best_ms, corr_stream_t stream);
@@ -218,7 +218,8 @@ int corr_tune_load(corr_ctx* ctx, const char* path);
  *   splits_a, splits_b: HOST int32[3], each in [1, the axis extent].
  *   out: HOST corr_max[n_a * n_b], out[i * n_b + j], sub-bricks numbered
  *        x-fastest (x, then y, then z).
- * CORR_EINVAL for bad splits or regions; synchronises `stream`.
+ * CORR_EINVAL for bad splits or regions, CORR_EUNSUPPORTED when a sub-brick
+ * pair has 2^31 or more point pairs; synchronises `stream`.
  */
 int corr_region_submax(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const int32_t* splits_a,
                        const corr_field* B, const corr_region* rb, const int32_t* splits_b, int prec,

@@ -62,7 +62,7 @@ enum WsSlot {
 
 // One autotuner record. kind 0: fastest small-K tile configuration of the
 // exhaustive Pearson contraction for (K, prec, na, nb). kind 1: fastest KSG
-// pairs-per-wave mapping for (K = M, prec = k); na = nb = 0.
+// workgroups-per-CU cap for (K = M, prec = k); na = nb = 0.
 struct corr_tune_rec {
     int kind;
     int K;
