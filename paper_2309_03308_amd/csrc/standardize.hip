@@ -6,6 +6,12 @@
 //   order (mean, then sum of squared deviations). Reads the member-major field
 //   with consecutive threads on consecutive points, so every member row is a
 //   coalesced load; loads are unrolled eight deep for memory parallelism.
+// stats_tile_kernel: the same two sums for long member rows (M >= 256, up to
+//   64 KiB of members per 16 points) over few points (up to 32768, a focus
+//   brick). A 256-thread workgroup stages all M members of 16 points in LDS
+//   with one read of the field (every thread keeps 32 loads in flight), then
+//   16 threads add them up in member order with the same expressions, so the
+//   results equal the one-thread-per-point kernel's bit for bit.
 // transpose_kernel: 64-point x 64-member LDS tile; loads member-major rows
 //   coalesced, normalises, and stores point-major rows (members contiguous),
 //   which is the layout both the pair kernels and the MFMA contraction read.
@@ -43,6 +49,96 @@ __global__ __launch_bounds__(64) void stats_kernel(const T* __restrict__ x, int6
     st.inv32[i] = pos ? (float)((ACC)1 / sqrt(q / (ACC)M)) : 0.0f;
     st.rs32[i] = pos ? (float)((ACC)1 / sqrt(q)) : 0.0f;
     st.sigma[i] = (float)sqrt(q / (ACC)M);
+}
+
+template <typename T>
+__device__ __forceinline__ float to_f32(T v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+
+// Points per workgroup of stats_tile_kernel, and the largest LDS stage it uses.
+constexpr int kTilePts = 16;
+constexpr int kTileLdsMax = 65536;
+
+template <typename T, typename ACC>
+__global__ __launch_bounds__(256) void stats_tile_kernel(const T* __restrict__ x, int64_t stride, int M, Box box,
+                                                         Stats st) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char stats_lds[];
+    T* tile = reinterpret_cast<T*>(stats_lds);  // [M][kTilePts]
+    constexpr int RW = 256 / kTilePts;          // member rows per sweep
+    constexpr int U = 32;                       // loads in flight per thread
+    const int tid = threadIdx.x, tx = tid % kTilePts, ty = tid / kTilePts;
+    const int64_t i = (int64_t)blockIdx.x * kTilePts + tx;
+    const bool valid = i < box.count();
+    const int64_t p = valid ? box.global(i) : 0;
+    // stage every member of the workgroup's points (one read of the field)
+    for (int m0 = ty; m0 < M; m0 += RW * U) {
+        T w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = m0 + RW * u;
+            w[u] = (valid && m < M) ? x[(int64_t)m * stride + p] : T(0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int m = m0 + RW * u;
+            if (m < M) tile[m * kTilePts + tx] = w[u];
+        }
+    }
+    __syncthreads();
+    if (tid >= kTilePts || !valid) return;
+    // the two sums in member order; LDS reads batched ahead of the additions
+    constexpr int B = 16;
+    ACC s = 0;
+    int m = 0;
+    for (; m + B <= M; m += B) {
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = to_f32(tile[(m + u) * kTilePts + tx]);
+#pragma unroll
+        for (int u = 0; u < B; ++u) s += (ACC)v[u];
+    }
+    for (; m < M; ++m) s += (ACC)to_f32(tile[m * kTilePts + tx]);
+    const ACC mean = s / (ACC)M;
+    ACC q = 0;
+    for (m = 0; m + B <= M; m += B) {
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = to_f32(tile[(m + u) * kTilePts + tx]);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            ACC d = (ACC)v[u] - mean;
+            q += d * d;
+        }
+    }
+    for (; m < M; ++m) {
+        ACC d = (ACC)to_f32(tile[m * kTilePts + tx]) - mean;
+        q += d * d;
+    }
+    bool pos = q > (ACC)0;
+    st.mu32[i] = (float)mean;
+    st.inv32[i] = pos ? (float)((ACC)1 / sqrt(q / (ACC)M)) : 0.0f;
+    st.rs32[i] = pos ? (float)((ACC)1 / sqrt(q)) : 0.0f;
+    st.sigma[i] = (float)sqrt(q / (ACC)M);
+}
+
+template <typename T, typename ACC>
+static void launch_stats_t(const T* x, int64_t stride, int M, const Box& box, Stats st, hipStream_t s) {
+    const int64_t n = box.count();
+    const size_t lds = (size_t)M * kTilePts * sizeof(T);
+    if (M >= 256 && n <= 32768 && lds <= (size_t)kTileLdsMax) {
+        // long rows over a few thousand points (a focus brick): 16 points
+        // per workgroup, so every CU takes part and all loads of a point's
+        // members are in flight together instead of one chain per thread
+        stats_tile_kernel<T, ACC><<<dim3((unsigned)((n + kTilePts - 1) / kTilePts)), 256, lds, s>>>(x, stride, M, box,
+                                                                                                    st);
+    } else {
+        // one thread per point in 64-thread workgroups: enough points to keep
+        // every CU busy (or short rows)
+        stats_kernel<T, ACC><<<dim3((unsigned)((n + 63) / 64)), 64, 0, s>>>(x, stride, M, box, st);
+    }
 }
 
 template <int FMT>
@@ -112,20 +208,17 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ x,
 int launch_stats(const corr_field& f, const Box& box, bool acc64, Stats st, hipStream_t s) {
     int64_t n = box.count();
     if (n == 0) return CORR_OK;
-    // one thread per point in 64-thread workgroups: a region of a few
-    // thousand points still spreads over every CU
-    dim3 grid((unsigned)((n + 63) / 64));
     int64_t stride = f.member_stride ? f.member_stride : (int64_t)f.nx * f.ny * f.nz;
     if (f.dtype == CORR_F32) {
         if (acc64)
-            stats_kernel<float, double><<<grid, 64, 0, s>>>((const float*)f.data, stride, f.M, box, st);
+            launch_stats_t<float, double>((const float*)f.data, stride, f.M, box, st, s);
         else
-            stats_kernel<float, float><<<grid, 64, 0, s>>>((const float*)f.data, stride, f.M, box, st);
+            launch_stats_t<float, float>((const float*)f.data, stride, f.M, box, st, s);
     } else {
         if (acc64)
-            stats_kernel<__half, double><<<grid, 64, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
+            launch_stats_t<__half, double>((const __half*)f.data, stride, f.M, box, st, s);
         else
-            stats_kernel<__half, float><<<grid, 64, 0, s>>>((const __half*)f.data, stride, f.M, box, st);
+            launch_stats_t<__half, float>((const __half*)f.data, stride, f.M, box, st, s);
     }
     CORR_LAUNCH_CHECK();
     return CORR_OK;
