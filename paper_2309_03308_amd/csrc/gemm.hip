@@ -29,6 +29,9 @@ namespace corr {
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
+// 16-byte staging word: a native vector, so the staging registers are plain
+// SSA values (a struct copy would go through a private-memory temporary)
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 
 constexpr int G_BM = 128, G_BN = 128;  // workgroup tile
 constexpr int G_WM = 2, G_WN = 2;      // 32x32 blocks per wave
@@ -44,6 +47,7 @@ struct GemmTraits {
     static constexpr int ROWB = KC * ES + 16;           // padded LDS row bytes
     static constexpr int PARTS = SPLIT ? 2 : 1;
     static constexpr int STAGE = PARTS * (G_BM + G_BN) * ROWB;  // bytes per LDS stage
+    static constexpr int PF = SPLIT ? 2 : 4;                     // chunks in flight in registers
 };
 
 template <int PREC>
@@ -73,8 +77,8 @@ __device__ __forceinline__ float wave_max(float v) {
 template <int PREC, int NRB>
 __device__ __forceinline__ void g_load(const char* a_hi, const char* a_lo, const char* b_hi, const char* b_lo,
                                        int64_t row0, int64_t col0, int64_t rowb_g, int c, int tid,
-                                       uint4 (&ra)[GemmTraits<PREC>::PARTS][2],
-                                       uint4 (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
+                                       u4_t (&ra)[GemmTraits<PREC>::PARTS][2],
+                                       u4_t (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
     using T = GemmTraits<PREC>;
     const int64_t kb = (int64_t)c * T::KC * T::ES;
 #pragma unroll
@@ -84,19 +88,19 @@ __device__ __forceinline__ void g_load(const char* a_hi, const char* a_lo, const
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int v = tid + G_THREADS * r;
-            ra[q][r] = *reinterpret_cast<const uint4*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+            ra[q][r] = *reinterpret_cast<const u4_t*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
         }
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
             const int v = tid + G_THREADS * r;
-            rb[q][r] = *reinterpret_cast<const uint4*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+            rb[q][r] = *reinterpret_cast<const u4_t*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
         }
     }
 }
 
 template <int PREC, int NRB>
-__device__ __forceinline__ void s_store(char* smem, int stage, int tid, const uint4 (&ra)[GemmTraits<PREC>::PARTS][2],
-                                        const uint4 (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
+__device__ __forceinline__ void s_store(char* smem, int stage, int tid, const u4_t (&ra)[GemmTraits<PREC>::PARTS][2],
+                                        const u4_t (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
     using T = GemmTraits<PREC>;
     char* base = smem + stage * T::STAGE;
 #pragma unroll
@@ -106,14 +110,80 @@ __device__ __forceinline__ void s_store(char* smem, int stage, int tid, const ui
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int v = tid + G_THREADS * r;
-            *reinterpret_cast<uint4*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
+            *reinterpret_cast<u4_t*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
         }
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
             const int v = tid + G_THREADS * r;
-            *reinterpret_cast<uint4*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
+            *reinterpret_cast<u4_t*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
         }
     }
+}
+
+// One chunk of a tile: products from LDS stage c & 1, then chunk c + 1
+// (held in register set (U + 1) % PF) into the other stage -- its readers
+// finished before the barrier that ended the previous chunk -- and that set
+// loads chunk c + 1 + PF. U is a template constant so every set index is
+// static and the sets stay in registers.
+template <int PREC, int NRB, int U>
+__device__ __forceinline__ void chunk_step(char* smem, int c, int n_chunks, int wr, int wc, int lane, int tid,
+                                           const char* a_hi, const char* a_lo, const char* b_hi, const char* b_lo,
+                                           int64_t row0, int64_t col0, int64_t rowb_g,
+                                           u4_t (&ra)[GemmTraits<PREC>::PF][GemmTraits<PREC>::PARTS][2],
+                                           u4_t (&rb)[GemmTraits<PREC>::PF][GemmTraits<PREC>::PARTS][NRB],
+                                           f16_t (&acc)[G_WM][G_WN]) {
+    using T = GemmTraits<PREC>;
+    constexpr int PF = T::PF;
+    const int stage = c & 1;
+    const char* base = smem + stage * T::STAGE;
+    const char* la_hi = base + (wr * 64 + (lane & 31)) * T::ROWB;
+    const char* lb_hi = base + G_BM * T::ROWB + (wc * 32 * G_WN + (lane & 31)) * T::ROWB;
+    const int half = lane >> 5;
+    if constexpr (T::F32) {
+        // 8 K-steps of 2 per chunk; lane reads k = 8q + 4*half + e
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+            float4 av[G_WM], bv[G_WN];
+#pragma unroll
+            for (int i = 0; i < G_WM; ++i)
+                av[i] = *reinterpret_cast<const float4*>(la_hi + i * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
+#pragma unroll
+            for (int j = 0; j < G_WN; ++j)
+                bv[j] = *reinterpret_cast<const float4*>(lb_hi + j * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < G_WN; ++j)
+                        mfma_step<PREC>(acc[i][j], (const char*)&av[i], (const char*)&bv[j], e);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < T::KC / 16; ++s) {
+            const int off = (s * 16 + half * 8) * 2;
+#pragma unroll
+            for (int i = 0; i < G_WM; ++i)
+#pragma unroll
+                for (int j = 0; j < G_WN; ++j) {
+                    const char* pa = la_hi + i * 32 * T::ROWB + off;
+                    const char* pb = lb_hi + j * 32 * T::ROWB + off;
+                    mfma_step<PREC>(acc[i][j], pa, pb, 0);
+                    if constexpr (T::SPLIT) {
+                        const int lo = (G_BM + G_BN) * T::ROWB;
+                        mfma_step<PREC>(acc[i][j], pa, pb + lo, 0);
+                        mfma_step<PREC>(acc[i][j], pa + lo, pb, 0);
+                    }
+                }
+        }
+    }
+    // Unconditional on purpose: after the last chunk the store is a dead
+    // copy into the idle stage and the load re-reads the last chunk; a
+    // branch here would make the compiler wait for every load in flight.
+    constexpr int nx = (U + 1) % PF;
+    s_store<PREC, NRB>(smem, stage ^ 1, tid, ra[nx], rb[nx]);
+    g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, min(c + 1 + PF, n_chunks - 1), tid, ra[nx], rb[nx]);
+    __syncthreads();
 }
 
 template <int PREC>
@@ -145,70 +215,44 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
         const int64_t row0 = (int64_t)ti * G_BM, col0 = (int64_t)tj * G_BN;
 
         // global -> register staging (per part): A tile = 128 rows x 64 B =
-        // 512 x 16 B, B tile = G_BN rows x 64 B
+        // 512 x 16 B, B tile = G_BN rows x 64 B. PF register sets keep the
+        // loads of the next PF chunks in flight, so a chunk's copy into LDS
+        // waits on a load issued PF chunks earlier (one chunk of products is
+        // far shorter than a load's latency).
         constexpr int NRB = G_BN * 4 / G_THREADS;
-        uint4 ra[T::PARTS][2], rb[T::PARTS][NRB];
+        constexpr int PF = T::PF;
+        static_assert(PF == 2 || PF == 4, "register sets: 2 or 4");
+        u4_t ra[PF][T::PARTS][2], rb[PF][T::PARTS][NRB];
         f16_t acc[G_WM][G_WN];
 #pragma unroll
         for (int i = 0; i < G_WM; ++i)
 #pragma unroll
             for (int j = 0; j < G_WN; ++j) acc[i][j] = f16_t{};
 
-        g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, 0, tid, ra, rb);
-        s_store<PREC, NRB>(smem, 0, tid, ra, rb);
-        __syncthreads();
-        for (int c = 0; c < n_chunks; ++c) {
-            const int stage = c & 1;
-            const char* base = smem + stage * T::STAGE;
-            const char* la_hi = base + (wr * 64 + (lane & 31)) * T::ROWB;
-            const char* lb_hi = base + G_BM * T::ROWB + (wc * 32 * G_WN + (lane & 31)) * T::ROWB;
-            const int half = lane >> 5;
-            if constexpr (T::F32) {
-                // 8 K-steps of 2 per chunk; lane reads k = 8q + 4*half + e
-#pragma unroll
-                for (int qq = 0; qq < 2; ++qq) {
-                    float4 av[G_WM], bv[G_WN];
-#pragma unroll
-                    for (int i = 0; i < G_WM; ++i)
-                        av[i] = *reinterpret_cast<const float4*>(la_hi + i * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
-#pragma unroll
-                    for (int j = 0; j < G_WN; ++j)
-                        bv[j] = *reinterpret_cast<const float4*>(lb_hi + j * 32 * T::ROWB + (qq * 8 + half * 4) * 4);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-#pragma unroll
-                        for (int i = 0; i < G_WM; ++i)
-#pragma unroll
-                            for (int j = 0; j < G_WN; ++j)
-                                mfma_step<PREC>(acc[i][j], (const char*)&av[i], (const char*)&bv[j], e);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < T::KC / 16; ++s) {
-                    const int off = (s * 16 + half * 8) * 2;
-#pragma unroll
-                    for (int i = 0; i < G_WM; ++i)
-#pragma unroll
-                        for (int j = 0; j < G_WN; ++j) {
-                            const char* pa = la_hi + i * 32 * T::ROWB + off;
-                            const char* pb = lb_hi + j * 32 * T::ROWB + off;
-                            mfma_step<PREC>(acc[i][j], pa, pb, 0);
-                            if constexpr (T::SPLIT) {
-                                const int lo = (G_BM + G_BN) * T::ROWB;
-                                mfma_step<PREC>(acc[i][j], pa, pb + lo, 0);
-                                mfma_step<PREC>(acc[i][j], pa + lo, pb, 0);
-                            }
-                        }
-                }
-            }
-            // next chunk into the other stage (its readers finished before the
-            // barrier that ended the previous iteration)
-            if (c + 1 < n_chunks) {
-                g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, c + 1, tid, ra, rb);
-                s_store<PREC, NRB>(smem, stage ^ 1, tid, ra, rb);
-            }
-            __syncthreads();
+        g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, 0, tid, ra[0], rb[0]);
+        s_store<PREC, NRB>(smem, 0, tid, ra[0], rb[0]);
+        // chunks 1..PF into sets 1 % PF .. PF % PF (n_chunks is a multiple
+        // of PF; a chunk index past the end re-reads the last chunk)
+        const int last = n_chunks - 1;
+        g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, min(1, last), tid, ra[1 % PF], rb[1 % PF]);
+        g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, min(2, last), tid, ra[2 % PF], rb[2 % PF]);
+        if constexpr (PF > 2) {
+            g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, min(3, last), tid, ra[3 % PF], rb[3 % PF]);
+            g_load<PREC, NRB>(a_hi, a_lo, b_hi, b_lo, row0, col0, rowb_g, min(4, last), tid, ra[4 % PF], rb[4 % PF]);
         }
+        __syncthreads();
+#define CHUNK(U)                                                                                                   \
+    chunk_step<PREC, NRB, (U) % PF>(smem, c0 + (U), n_chunks, wr, wc, lane, tid, a_hi, a_lo, b_hi, b_lo, row0, col0, \
+                                    rowb_g, ra, rb, acc)
+        for (int c0 = 0; c0 < n_chunks; c0 += PF) {
+            CHUNK(0);
+            CHUNK(1);
+            if constexpr (PF > 2) {
+                CHUNK(2);
+                CHUNK(3);
+            }
+        }
+#undef CHUNK
 
         // ---- epilogue: fold |r| of this tile into the wave's running max
         const bool edge = (row0 + G_BM > g.na) || (col0 + G_BN > g.nb);
@@ -280,6 +324,7 @@ static int launch_p(const GemmArgs& g, int num_cus, hipStream_t s) {
     int64_t grid = (int64_t)num_cus * 2;
     if (grid > n_tiles) grid = n_tiles;
     const size_t lds = 2 * (size_t)T::STAGE;
+    if (g.K <= 0 || g.K % (T::KC * T::PF)) return fail(CORR_EINVAL, "contraction: K not a multiple of the chunk group");
     int rc = kernel_setup((const void*)gemm_max_kernel<PREC>, lds, G_THREADS, nullptr);
     if (rc) return rc;
     gemm_max_kernel<PREC><<<dim3((unsigned)grid), G_THREADS, lds, s>>>(g, n_ti, n_tj);
@@ -301,6 +346,14 @@ int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s) {
 
 int gemm_row_pad() { return G_BM; }
 int gemm_col_pad() { return G_BN; }
-int gemm_k_pad(int prec) { return prec == CORR_PREC_F32 ? GemmTraits<CORR_PREC_F32>::KC : GemmTraits<CORR_PREC_F16>::KC; }
+int gemm_k_pad(int prec) {
+    // K is consumed in groups of PF chunks
+    switch (prec) {
+        case CORR_PREC_F32: return GemmTraits<CORR_PREC_F32>::KC * GemmTraits<CORR_PREC_F32>::PF;
+        case CORR_PREC_F16X3: return GemmTraits<CORR_PREC_F16X3>::KC * GemmTraits<CORR_PREC_F16X3>::PF;
+        case CORR_PREC_BF16X3: return GemmTraits<CORR_PREC_BF16X3>::KC * GemmTraits<CORR_PREC_BF16X3>::PF;
+        default: return GemmTraits<CORR_PREC_F16>::KC * GemmTraits<CORR_PREC_F16>::PF;
+    }
+}
 
 }  // namespace corr
