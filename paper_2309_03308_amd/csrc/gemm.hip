@@ -10,13 +10,15 @@
 //  - workgroup = 4 waves (2 x 2), workgroup tile 128 (A rows) x 128 (B rows),
 //    wave tile 64 x 64 = 2 x 2 blocks of v_mfma_f32_32x32x16_{f16,bf16}
 //    (v_mfma_f32_32x32x2_f32 for FP32 operands), FP32 accumulators;
-//  - K is consumed in chunks staged through LDS, double-buffered: chunk c+1
-//    is copied into the other stage right after chunk c's products are
-//    issued (other resident waves cover the load latency); LDS rows are
-//    padded by 16 bytes so the 16-byte operand reads are conflict-free;
+//  - K is consumed in chunks (64 B per row; 128 B for single-pass 16-bit
+//    operands) staged through LDS, double-buffered: chunk c+1 is copied into
+//    the other stage after chunk c's products are issued, from registers
+//    loaded several chunks earlier; LDS rows are padded by 16 bytes so the
+//    16-byte operand reads are conflict-free;
 //  - split modes hold hi and lo parts and issue hi.hi + hi.lo + lo.hi;
-//  - persistent workgroups walk tiles in an XCD-grouped order, so the
-//    workgroups resident on one XCD (one L2) work on neighbouring tiles;
+//  - persistent workgroups walk tiles in an XCD-grouped order, and tiles
+//    are numbered in 8-row groups, so the workgroups resident on one XCD
+//    (one L2) work on an 8 x 8 block of tiles;
 //  - epilogue: per-lane max of |r| (v_max3 with abs modifiers), wave max by
 //    shuffles; only when a tile beats the wave's best so far (rare after the
 //    first tiles) does the wave locate the element, picking the smallest
@@ -43,11 +45,16 @@ struct GemmTraits {
     static constexpr bool SPLIT = PREC == CORR_PREC_F16X3 || PREC == CORR_PREC_BF16X3;
     static constexpr bool BF = PREC == CORR_PREC_BF16 || PREC == CORR_PREC_BF16X3;
     static constexpr int ES = F32 ? 4 : 2;              // element bytes
-    static constexpr int KC = F32 ? 16 : 32;            // chunk length (elements) = 64 bytes per row
+    // chunk length (elements): 64 bytes per row for FP32 and the split
+    // modes (two parts), 128 bytes for single-pass 16-bit operands
+    static constexpr int KC = F32 ? 16 : (SPLIT ? 32 : 64);
+    static constexpr int QW = KC * ES / 16;             // 16-byte words per row and chunk
     static constexpr int ROWB = KC * ES + 16;           // padded LDS row bytes
     static constexpr int PARTS = SPLIT ? 2 : 1;
     static constexpr int STAGE = PARTS * (G_BM + G_BN) * ROWB;  // bytes per LDS stage
-    static constexpr int PF = SPLIT ? 2 : 4;                     // chunks in flight in registers
+    static constexpr int PF = F32 ? 4 : 2;                       // chunks in flight in registers
+    static constexpr int NRA = G_BM * QW / G_THREADS;            // A words per thread and part
+    static constexpr int NRB = G_BN * QW / G_THREADS;            // B words per thread and part
 };
 
 template <int PREC>
@@ -77,7 +84,7 @@ __device__ __forceinline__ float wave_max(float v) {
 template <int PREC, int NRB>
 __device__ __forceinline__ void g_load(const char* a_hi, const char* a_lo, const char* b_hi, const char* b_lo,
                                        int64_t row0, int64_t col0, int64_t rowb_g, int c, int tid,
-                                       u4_t (&ra)[GemmTraits<PREC>::PARTS][2],
+                                       u4_t (&ra)[GemmTraits<PREC>::PARTS][GemmTraits<PREC>::NRA],
                                        u4_t (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
     using T = GemmTraits<PREC>;
     const int64_t kb = (int64_t)c * T::KC * T::ES;
@@ -86,20 +93,21 @@ __device__ __forceinline__ void g_load(const char* a_hi, const char* a_lo, const
         const char* sa = q ? a_lo : a_hi;
         const char* sb = q ? b_lo : b_hi;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < T::NRA; ++r) {
             const int v = tid + G_THREADS * r;
-            ra[q][r] = *reinterpret_cast<const u4_t*>(sa + (row0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+            ra[q][r] = *reinterpret_cast<const u4_t*>(sa + (row0 + v / T::QW) * rowb_g + kb + (v % T::QW) * 16);
         }
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
             const int v = tid + G_THREADS * r;
-            rb[q][r] = *reinterpret_cast<const u4_t*>(sb + (col0 + (v >> 2)) * rowb_g + kb + (v & 3) * 16);
+            rb[q][r] = *reinterpret_cast<const u4_t*>(sb + (col0 + v / T::QW) * rowb_g + kb + (v % T::QW) * 16);
         }
     }
 }
 
 template <int PREC, int NRB>
-__device__ __forceinline__ void s_store(char* smem, int stage, int tid, const u4_t (&ra)[GemmTraits<PREC>::PARTS][2],
+__device__ __forceinline__ void s_store(char* smem, int stage, int tid,
+                                        const u4_t (&ra)[GemmTraits<PREC>::PARTS][GemmTraits<PREC>::NRA],
                                         const u4_t (&rb)[GemmTraits<PREC>::PARTS][NRB]) {
     using T = GemmTraits<PREC>;
     char* base = smem + stage * T::STAGE;
@@ -108,14 +116,14 @@ __device__ __forceinline__ void s_store(char* smem, int stage, int tid, const u4
         char* la = base + q * (G_BM + G_BN) * T::ROWB;
         char* lb = la + G_BM * T::ROWB;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < T::NRA; ++r) {
             const int v = tid + G_THREADS * r;
-            *reinterpret_cast<u4_t*>(la + (v >> 2) * T::ROWB + (v & 3) * 16) = ra[q][r];
+            *reinterpret_cast<u4_t*>(la + (v / T::QW) * T::ROWB + (v % T::QW) * 16) = ra[q][r];
         }
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
             const int v = tid + G_THREADS * r;
-            *reinterpret_cast<u4_t*>(lb + (v >> 2) * T::ROWB + (v & 3) * 16) = rb[q][r];
+            *reinterpret_cast<u4_t*>(lb + (v / T::QW) * T::ROWB + (v % T::QW) * 16) = rb[q][r];
         }
     }
 }
@@ -129,7 +137,7 @@ template <int PREC, int NRB, int U>
 __device__ __forceinline__ void chunk_step(char* smem, int c, int n_chunks, int wr, int wc, int lane, int tid,
                                            const char* a_hi, const char* a_lo, const char* b_hi, const char* b_lo,
                                            int64_t row0, int64_t col0, int64_t rowb_g,
-                                           u4_t (&ra)[GemmTraits<PREC>::PF][GemmTraits<PREC>::PARTS][2],
+                                           u4_t (&ra)[GemmTraits<PREC>::PF][GemmTraits<PREC>::PARTS][GemmTraits<PREC>::NRA],
                                            u4_t (&rb)[GemmTraits<PREC>::PF][GemmTraits<PREC>::PARTS][NRB],
                                            f16_t (&acc)[G_WM][G_WN]) {
     using T = GemmTraits<PREC>;
@@ -211,18 +219,24 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
     const char* b_lo = (const char*)g.b_lo;
 
     for (int64_t tile = lg; tile < n_tiles; tile += G) {
-        const int ti = (int)(tile / n_tj), tj = (int)(tile % n_tj);
+        // groups of 8 tile rows walked column by column: 64 consecutive
+        // tiles (the workgroups resident on one XCD at a time) form an 8 x 8
+        // block and share 8 A and 8 B panels in that XCD's L2
+        const int64_t grp = tile / (8 * (int64_t)n_tj);
+        const int first = (int)grp * 8, gsz = min(n_ti - first, 8);
+        const int64_t in = tile - grp * 8 * (int64_t)n_tj;
+        const int ti = first + (int)(in % gsz), tj = (int)(in / gsz);
         const int64_t row0 = (int64_t)ti * G_BM, col0 = (int64_t)tj * G_BN;
 
-        // global -> register staging (per part): A tile = 128 rows x 64 B =
-        // 512 x 16 B, B tile = G_BN rows x 64 B. PF register sets keep the
+        // global -> register staging (per part): A tile = 128 rows x KC
+        // elements in 16-byte words, B tile likewise. PF register sets keep the
         // loads of the next PF chunks in flight, so a chunk's copy into LDS
         // waits on a load issued PF chunks earlier (one chunk of products is
         // far shorter than a load's latency).
-        constexpr int NRB = G_BN * 4 / G_THREADS;
+        constexpr int NRB = T::NRB;
         constexpr int PF = T::PF;
         static_assert(PF == 2 || PF == 4, "register sets: 2 or 4");
-        u4_t ra[PF][T::PARTS][2], rb[PF][T::PARTS][NRB];
+        u4_t ra[PF][T::PARTS][T::NRA], rb[PF][T::PARTS][NRB];
         f16_t acc[G_WM][G_WN];
 #pragma unroll
         for (int i = 0; i < G_WM; ++i)
