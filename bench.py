@@ -171,8 +171,8 @@ def main():
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the hot path has no multi-GPU mode in this build "
-              "(region pairs would shard across GPUs; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the hot path has no multi-GPU mode "
+              "(region pairs would shard across GPUs, one process per GPU).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -21,7 +21,7 @@
  *  - Arguments are validated on the host before anything is enqueued:
  *    CORR_EINVAL for bad arguments (null pointers, M < 2, k outside
  *    [1, M-1], regions outside the grid, n < 0, fields of different M),
- *    CORR_EUNSUPPORTED for a dtype / precision / size this build does not
+ *    CORR_EUNSUPPORTED for a dtype / precision / size the library does not
  *    handle, CORR_ENOMEM when a workspace cannot be allocated, CORR_EHIP for
  *    a failed HIP call (its message is kept in corr_last_error()).
  *    No C++ exception crosses this ABI.

@@ -14,8 +14,7 @@
  *     strict marginal counts n_x,i and n_y,i, and the digamma sum; the digamma
  *     function is the logarithmic derivative of Gamma (Eq. 2).
  *
- * Readings where the paper is silent or garbled (each also listed in the
- * design notes):
+ * Readings where the paper is silent or garbled:
  *   - the KSG sum is (1/n) * sum_i [psi(n_x,i) + psi(n_y,i)] (brackets missing
  *     in the printed formula);
  *   - marginal counts exclude the sample itself and enter as psi(n + 1), which
