@@ -28,8 +28,15 @@
  * 2 uniform candidates, 3 local candidates, 4 rounding.
  *
  * All pairs advance together: bos_sample_step runs one iteration for every
- * pair that still has work, as one persistent kernel (workgroups take pairs
- * from an atomic counter) captured once into a HIP graph and replayed.
+ * pair that still has work, as one persistent kernel whose workgroups walk
+ * the iteration's pair list (costliest pairs first, static stride) followed
+ * by a one-thread kernel that advances the device-side iteration counter.
+ * The two launches are captured once into a HIP graph and replayed
+ * (BOS_LAUNCH_GRAPH, the default) or launched directly (BOS_LAUNCH_PLAIN);
+ * both give bit-identical results.
+ * Calls that wait for the GPU (bos_create, bos_run, bos_results,
+ * bos_history, bos_save, bos_load, bos_destroy) poll with a deadline
+ * (bos_set_launch) and return CORR_EHIP when it passes instead of blocking.
  * Ownership: bos_state owns its device state and workspaces; it borrows the
  * fields (their device memory must stay valid until bos_destroy) and the
  * corr_ctx. Errors as in corr.h.
@@ -61,6 +68,9 @@ typedef struct bos_config {
 
 typedef struct bos_state bos_state;
 
+/* Launch modes of an iteration (bos_set_launch). */
+enum { BOS_LAUNCH_GRAPH = 0, BOS_LAUNCH_PLAIN = 1 };
+
 /* Fill a config with the defaults listed above (measure CORR_PEARSON, k 10,
  * n_init 20, n_total 100, n_uniform 384, n_local 128, seed 1). */
 void bos_config_default(bos_config* cfg);
@@ -89,14 +99,23 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
 int bos_set_prior(bos_state* st, const float* cells);
 
 /*
- * One iteration for every pair with work left: the first call evaluates the
- * initial designs, later calls one batch per pair. n_active_out (HOST,
- * nullable; the call then synchronises `stream`) receives the number of
- * pairs that still have batches left.
+ * Launch mode (BOS_LAUNCH_GRAPH or BOS_LAUNCH_PLAIN) and the longest time in
+ * seconds (> 0; default 300) that a call waits for the GPU before it returns
+ * CORR_EHIP. May be called at any time; a captured graph is kept.
+ */
+int bos_set_launch(bos_state* st, int32_t mode, double timeout_s);
+
+/*
+ * One iteration for every pair with work left, enqueued on `stream` (the
+ * call does not wait for it): the first call evaluates the initial designs,
+ * later calls one batch per pair. n_active_out (HOST, nullable) receives the
+ * number of pairs that still have batches left after this iteration; it
+ * follows from the schedule, which the host knows, so no read-back is needed.
+ * After the last iteration further calls do nothing and report 0.
  */
 int bos_sample_step(bos_state* st, corr_stream_t stream, int32_t* n_active_out);
 
-/* Run steps until no pair is active. */
+/* Run steps until no pair is active, then wait for them (with the deadline). */
 int bos_run(bos_state* st, corr_stream_t stream);
 
 /* Per pair: maximum found (value, signed value at it, global pa/pb) and the
@@ -116,7 +135,9 @@ int bos_history(bos_state* st, int32_t pair, int32_t* cells, float* values, int3
 int bos_save(bos_state* st, const char* path, corr_stream_t stream);
 int bos_load(bos_state* st, const char* path, corr_stream_t stream);
 
-/* Free the state (waits for its work). NULL is allowed. */
+/* Free the state after its enqueued work has finished (waiting with the
+ * deadline; if the deadline passes the device buffers are left allocated
+ * rather than freed under running work). NULL is allowed. */
 void bos_destroy(bos_state* st);
 
 #ifdef __cplusplus

@@ -336,6 +336,10 @@ class Bos:
         except Exception:
             pass
 
+    def bos_set_launch(self, mode="graph", timeout_s=300.0):
+        """Launch iterations through a captured HIP graph or directly; bound every wait."""
+        _lib.check(self.L.bos_set_launch(self.h, _lib.BOS_LAUNCH[mode], float(timeout_s)))
+
     def bos_set_prior(self, cells):
         import numpy as np
         c = np.ascontiguousarray(np.asarray(cells, dtype=np.float32).reshape(self.n_pairs, 6))

@@ -20,6 +20,7 @@ MEASURE = {"pearson": 0, "ksg": 1}
 SAMPLER = {"uniform": 0, "halton": 1, "plastic": 2}
 STRATEGY = {0: "bos", 1: "random", 2: "exhaustive"}
 CORR_KSG_RAW = 1
+BOS_LAUNCH = {"graph": 0, "plain": 1}
 
 
 class corr_field(ctypes.Structure):
@@ -78,6 +79,7 @@ SIGNATURES = {
     "bos_create": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), ctypes.POINTER(corr_region),
                         _I32, _P, _I32, ctypes.POINTER(bos_config), ctypes.POINTER(_P), _P]),
     "bos_set_prior": (_I, [_P, _P]),
+    "bos_set_launch": (_I, [_P, _I32, ctypes.c_double]),
     "bos_sample_step": (_I, [_P, _P, ctypes.POINTER(_I32)]),
     "bos_run": (_I, [_P, _P]),
     "bos_results": (_I, [_P, ctypes.POINTER(corr_max), _P]),

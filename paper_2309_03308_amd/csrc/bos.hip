@@ -1,7 +1,11 @@
 // Batched Bayesian optimal sampling of region-pair maxima (Sec. 3.1).
 //
-// One persistent kernel per iteration. Workgroups (256 threads) take region
-// pairs from an atomic counter; for a pair the workgroup
+// One persistent kernel per iteration. The host knows every pair's batch
+// schedule (it is drawn from the seed) and lists, per iteration, the pairs
+// that still sample there, costliest first; workgroups (256 threads) walk
+// that list with a static stride, so the loop over pairs, like every loop
+// that contains a barrier, runs on wave-uniform (scalar) values. For a pair
+// the workgroup
 //   - rebuilds the Gaussian process of the pair's observations in LDS (FP64
 //     Matern-5/2 covariance, packed lower Cholesky factor, solves by one
 //     wave with shuffles),
@@ -18,12 +22,23 @@
 //     FP32 dot products of standardised rows; KSG: one wave per cell, the
 //     same exact max-norm selection and sorted-marginal counts as the pair
 //     kernel), then appends them to the pair's observations.
-// The iteration (counter reset, kernel, iteration advance) is captured into
-// a HIP graph once and replayed by every bos_sample_step.
+// An iteration is the kernel followed by a one-thread kernel that advances
+// the device-side iteration counter, so the same two launches are replayed
+// unchanged: captured once into a HIP graph (default) or launched directly.
+//
+// Why the pair loop takes no work from an atomic counter: with the fetch
+// (thread 0 only) at the head of the loop and the active-pair count (thread 0
+// only) at its tail, the compiler merged the two thread-0 branches across the
+// back edge into a nested loop in which only thread 0's lane left to fetch
+// the next pair while all other lanes went back to the head barrier with the
+// old pair -- a livelock on the first pair. Uniform loop control rules that
+// shape out; a CPU test checks the compiled kernels for it.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/bos.h"
@@ -64,14 +79,16 @@ struct BosDev {
     float* sv;       // [n_pairs][n_total] signed value (r or MI)
     int* n_obs;
     int* slot;
-    int* sched;      // [n_pairs][16]
-    int* n_sched;
+    const int* sched;    // [n_pairs][16] batch sizes (host-drawn)
+    const int* n_sched;  // batches per pair
     int* best;
     const float* prior;  // [n_pairs][6] or NULL
     // control
-    int* iter;
-    int* work;
-    int* n_active;
+    int* iter;                // device iteration counter (0: initial design)
+    const int* list;          // pairs of every iteration, concatenated
+    const int* list_start;    // [n_iter] offset of iteration t's pairs in list
+    const int* list_count;    // [n_iter] number of pairs sampling in iteration t
+    int n_iter;               // iterations listed (initial design included)
     double* qbuf;  // per workgroup [n_total][C]
     // LDS layout (in doubles)
     int off_L, off_X, off_y, off_a, off_th, off_mu, off_s2, off_qs, off_pk, off_red, off_misc, lds_doubles;
@@ -90,6 +107,11 @@ __device__ inline double matern52(const double* a, const double* b, double inv_l
 }
 
 __device__ inline int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// The value of the first active lane: every loop or branch that encloses a
+// barrier takes its bounds through this, so the compiler keeps its control
+// in scalar registers (all lanes hold the same value there anyway).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <int KP1>
 __device__ __forceinline__ void bos_topk_insert(float (&t)[KP1], float d) {
@@ -236,7 +258,7 @@ __device__ int block_argmax(double v, int idx, double* red_v, int* red_i) {
         }
         __syncthreads();
     }
-    const int r = red_i[0];
+    const int r = uni(red_i[0]);
     __syncthreads();
     return r;
 }
@@ -286,7 +308,7 @@ __device__ void bos_init_pair(const BosDev& d, int pair, double* sm) {
         *nuniq = n;
     }
     __syncthreads();
-    const int n = *nuniq;
+    const int n = uni(*nuniq);
     eval_cells<KP1>(d, pair, uniq, n, vals, svals, reinterpret_cast<float*>(sm + d.off_th));
     __syncthreads();
     const int base = pair * d.n_total;
@@ -302,24 +324,14 @@ __device__ void bos_init_pair(const BosDev& d, int pair, double* sm) {
         d.best[pair] = b;
         d.n_obs[pair] = n;
         d.slot[pair] = d.n_init;
-        // uneven schedule: batches of 8 * p, p = 1 + floor(u * min(8, units left))
-        int units = (d.n_total - d.n_init) / 8, i = 0;
-        while (units > 0 && i < 16) {
-            const int mx = units < 8 ? units : 8;
-            const int p = 1 + (int)(ph_uniform(d.seed, pair, ST_SCHED, i, 0) * mx);
-            d.sched[pair * 16 + i] = 8 * p;
-            units -= p;
-            ++i;
-        }
-        d.n_sched[pair] = i;
     }
 }
 
 template <int KP1>
 __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n = d.n_obs[pair];
-    const int b = d.sched[pair * 16 + t];
+    const int n = uni(d.n_obs[pair]);
+    const int b = uni(d.sched[pair * 16 + t]);
     const int C = d.C;
     const int base = pair * d.n_total;
     double* L = sm + d.off_L;
@@ -419,7 +431,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         }
     }
     // ---- candidates
-    const int bi = d.best[pair];
+    const int bi = uni(d.best[pair]);
     for (int c = tid; c < C; c += 256) {
         taken[c] = 0;
         for (int a = 0; a < 6; ++a) {
@@ -490,7 +502,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         __syncthreads();
     }
     // ---- rounding (Bernoulli of the fractional part) and dedupe
-    const int slot0 = d.slot[pair];
+    const int slot0 = uni(d.slot[pair]);
     for (int m = tid; m < b; m += 256) {
         for (int a = 0; a < 6; ++a) {
             const double v = pk[6 * m + a];
@@ -527,7 +539,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         *nnew = q;
     }
     __syncthreads();
-    const int nn = *nnew;
+    const int nn = uni(*nnew);
     // ---- evaluate and append (th / mu / s2 space is free now)
     double* vals = mu;
     float* svals = reinterpret_cast<float*>(s2);
@@ -555,30 +567,20 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
 template <int KP1>
 __global__ __launch_bounds__(256) void bos_kernel(BosDev d) {
     extern __shared__ __attribute__((aligned(16))) double sm[];
-    __shared__ int s_pair;
-    const int it = *d.iter;
-    for (;;) {
-        if (threadIdx.x == 0) s_pair = atomicAdd(d.work, 1);
-        __syncthreads();
-        const int pair = s_pair;
-        __syncthreads();
-        if (pair >= d.n_pairs) break;
-        if (it == 0) {
+    const int it = uni(*d.iter);
+    if (it >= d.n_iter) return;  // every pair is done
+    const int start = uni(d.list_start[it]), count = uni(d.list_count[it]);
+    // static stride over the iteration's pairs: at most ceil(count / grid) trips
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        const int pair = uni(d.list[start + q]);
+        if (it == 0)
             bos_init_pair<KP1>(d, pair, sm);
-        } else if (it - 1 < d.n_sched[pair]) {
+        else
             bos_batch_pair<KP1>(d, pair, it - 1, sm);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && it < d.n_sched[pair]) atomicAdd(d.n_active, 1);
+        __syncthreads();  // the LDS is reused by the next pair
     }
 }
 
-__global__ void bos_reset_kernel(int* work, int* n_active) {
-    if (threadIdx.x == 0) {
-        *work = 0;
-        *n_active = 0;
-    }
-}
 __global__ void bos_advance_kernel(int* iter) {
     if (threadIdx.x == 0) *iter += 1;
 }
@@ -599,16 +601,26 @@ struct bos_state {
     int16_t* cells = nullptr;
     double* yv = nullptr;
     float* sv = nullptr;
-    int* ints = nullptr;  // n_obs, slot, best, n_sched, sched[16], iter, work, n_active
+    int* ints = nullptr;  // n_obs, slot, best, n_sched, sched[16], iter
+    int* lists = nullptr;  // list_start[n_iter], list_count[n_iter], list[]
     float* prior = nullptr;
     Box* boxes = nullptr;  // [2][n_pairs]
     std::vector<Box> hb;   // host copy of the pair boxes
+    std::vector<int> h_nsched, h_sched;  // host copy of the schedule
+    int n_iter = 0;
+    // launch
+    int mode = BOS_LAUNCH_GRAPH;
+    double timeout_s = 300.0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;  // stream of the latest enqueued work
+    bool used = false;
     int steps = 0;
     bool done = false;
 };
+
+static size_t ints_count(size_t np) { return np * 20 + 8; }
 
 static int bos_alloc(bos_state* st, size_t bytes, void** p) {
     hipError_t e = hipMalloc(p, bytes);
@@ -617,6 +629,36 @@ static int bos_alloc(bos_state* st, size_t bytes, void** p) {
         return fail(CORR_ENOMEM, "bos: allocation of " + std::to_string(bytes) + " bytes failed");
     }
     st->allocs.push_back(*p);
+    return CORR_OK;
+}
+
+// Wait for the work enqueued on `s` so far, polling an event, and give up with
+// CORR_EHIP after `timeout_s` seconds instead of blocking without bound.
+static int wait_deadline(hipStream_t s, double timeout_s, const char* what) {
+    hipEvent_t ev = nullptr;
+    CORR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, s);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return fail(CORR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        e = hipEventQuery(ev);
+        if (e == hipSuccess) break;
+        if (e != hipErrorNotReady) {
+            (void)hipEventDestroy(ev);
+            return fail(CORR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+        }
+        const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (dt > timeout_s) {
+            (void)hipEventDestroy(ev);
+            return fail(CORR_EHIP, std::string(what) + ": the GPU work did not finish within " +
+                                       std::to_string(timeout_s) + " s");
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.01 ? 20 : 500));
+    }
+    (void)hipEventDestroy(ev);
     return CORR_OK;
 }
 
@@ -672,6 +714,57 @@ static void bos_launch_kernel(bos_state* st, hipStream_t s) {
     }
 }
 
+// The uneven batch schedule of one pair (drawn from the seed): batches of
+// 8 * p, p = 1 + floor(u * min(8, units left)), until the n_total - n_init
+// acquired samples are placed. Returns the number of batches.
+static int pair_schedule(const bos_config& c, int pair, int* sched16) {
+    int units = (c.n_total - c.n_init) / 8, i = 0;
+    while (units > 0 && i < 16) {
+        const int mx = units < 8 ? units : 8;
+        const int p = 1 + (int)(ph_uniform(c.seed, (uint64_t)pair, ST_SCHED, (uint64_t)i, 0) * mx);
+        sched16[i] = 8 * p;
+        units -= p;
+        ++i;
+    }
+    return i;
+}
+
+// Per iteration, the pairs that sample in it, costliest first (the estimate
+// counts the posterior solves, the believer updates and the factorisation at
+// the pair's largest possible observation count).
+static void build_lists(const bos_config& c, int np, const std::vector<int>& nsched, const std::vector<int>& sched,
+                        int* n_iter, std::vector<int>& out) {
+    int T = 0;
+    for (int p = 0; p < np; ++p) T = std::max(T, nsched[p]);
+    T += 1;  // the initial design
+    std::vector<int> start(T), count(T), list;
+    list.reserve((size_t)np * T);
+    const double C = (double)(c.n_uniform + c.n_local);
+    for (int t = 0; t < T; ++t) {
+        start[t] = (int)list.size();
+        std::vector<std::pair<double, int>> cost;
+        for (int p = 0; p < np; ++p) {
+            if (t == 0) {
+                cost.emplace_back(0.0, p);
+            } else if (t - 1 < nsched[p]) {
+                double n = c.n_init;
+                for (int u = 0; u < t - 1; ++u) n += sched[(size_t)p * 16 + u];
+                const double b = sched[(size_t)p * 16 + t - 1];
+                cost.emplace_back(C * (0.5 * n * n + 6.0 * n) + b * C * (n + 0.5 * b) + n * n * n / 6.0, p);
+            }
+        }
+        std::stable_sort(cost.begin(), cost.end(),
+                         [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+        for (auto& e : cost) list.push_back(e.second);
+        count[t] = (int)list.size() - start[t];
+    }
+    *n_iter = T;
+    out.clear();
+    out.insert(out.end(), start.begin(), start.end());
+    out.insert(out.end(), count.begin(), count.end());
+    out.insert(out.end(), list.begin(), list.end());
+}
+
 extern "C" {
 
 void bos_config_default(bos_config* c) {
@@ -691,7 +784,9 @@ void bos_config_default(bos_config* c) {
 
 void bos_destroy(bos_state* st) {
     if (!st) return;
-    (void)hipDeviceSynchronize();
+    // never free memory that enqueued work may still use: if that work does
+    // not finish in time the buffers are left allocated
+    if (st->used && wait_deadline(st->last, st->timeout_s, "bos_destroy") != CORR_OK) return;
     if (st->exec) (void)hipGraphExecDestroy(st->exec);
     if (st->graph) (void)hipGraphDestroy(st->graph);
     if (st->cap) (void)hipStreamDestroy(st->cap);
@@ -752,6 +847,7 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
         st->hb[n_pairs + p] = Box{rb.x0, rb.y0, rb.z0, rb.dx, rb.dy, rb.dz, B->nx, B->ny};
     }
     hipStream_t s = (hipStream_t)stream;
+    st->last = s;
     int rc = CORR_OK;
     BosDev& d = st->d;
     d.measure = c.measure;
@@ -772,8 +868,9 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     // standardised rows
     const bool ksg = c.measure == CORR_KSG;
     const int fmt = ksg ? ZF_KSG : ZF_F32;
-    const int64_t ld = ksg ? ((A->M + 3) / 4 * 4) : ((A->M + 3) / 4 * 4);
+    const int64_t ld = (A->M + 3) / 4 * 4;
     float *ra_rows, *ra_stats, *ra_sorted, *rb_rows, *rb_stats, *rb_sorted;
+    st->used = true;
     rc = bos_standardize(st, *A, fmt, ld, s, &ra_rows, &ra_stats, &ra_sorted);
     if (!rc) {
         const bool same = A->data == B->data && A->dtype == B->dtype && A->nx == B->nx && A->ny == B->ny &&
@@ -799,12 +896,24 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     d.p2 = ksg ? ksg_p2(A->M) : 0;
     d.inv_a = ra_stats + na_pts;  // stats layout: mu32, inv32, rs32, sigma
     d.inv_b = rb_stats + nb_pts;
-    // state arrays
+    // host schedule and per-iteration pair lists
     const size_t np = (size_t)n_pairs;
+    std::vector<int> hints(ints_count(np), 0);
+    st->h_nsched.assign(np, 0);
+    st->h_sched.assign(np * 16, 0);
+    for (int p = 0; p < n_pairs; ++p) st->h_nsched[p] = pair_schedule(c, p, &st->h_sched[(size_t)p * 16]);
+    for (size_t p = 0; p < np; ++p) {
+        hints[3 * np + p] = st->h_nsched[p];
+        for (int i = 0; i < 16; ++i) hints[4 * np + 16 * p + i] = st->h_sched[16 * p + i];
+    }
+    std::vector<int> hl;
+    build_lists(c, n_pairs, st->h_nsched, st->h_sched, &st->n_iter, hl);
+    // state arrays
     if (!rc) rc = bos_alloc(st, sizeof(int16_t) * np * c.n_total * 6, (void**)&st->cells);
     if (!rc) rc = bos_alloc(st, sizeof(double) * np * c.n_total, (void**)&st->yv);
     if (!rc) rc = bos_alloc(st, sizeof(float) * np * c.n_total, (void**)&st->sv);
-    if (!rc) rc = bos_alloc(st, sizeof(int) * (np * 20 + 8), (void**)&st->ints);
+    if (!rc) rc = bos_alloc(st, sizeof(int) * ints_count(np), (void**)&st->ints);
+    if (!rc) rc = bos_alloc(st, sizeof(int) * hl.size(), (void**)&st->lists);
     if (!rc) rc = bos_alloc(st, sizeof(float) * np * 6, (void**)&st->prior);
     if (!rc) rc = bos_alloc(st, sizeof(Box) * 2 * np, (void**)&st->boxes);
     if (rc) {
@@ -820,8 +929,10 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     d.n_sched = st->ints + 3 * np;
     d.sched = st->ints + 4 * np;  // [np][16]
     d.iter = st->ints + 20 * np;
-    d.work = d.iter + 1;
-    d.n_active = d.iter + 2;
+    d.n_iter = st->n_iter;
+    d.list_start = st->lists;
+    d.list_count = st->lists + st->n_iter;
+    d.list = st->lists + 2 * st->n_iter;
     d.prior = nullptr;
     d.ba = st->boxes;
     d.bb = st->boxes + np;
@@ -853,24 +964,39 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
         bos_destroy(st);
         return fail(CORR_EUNSUPPORTED, "bos_create: configuration needs more than 160 KiB of LDS");
     }
-    const int per_cu = std::max(1, (int)((160 * 1024) / (st->lds_bytes + 1024)));
-    st->grid = std::min(n_pairs, ctx->num_cus * std::min(per_cu, 2));
+    int per_cu = 1;
+    if ((rc = kernel_setup(bos_kernel_for(st->kp1), st->lds_bytes, 256, &per_cu))) {
+        bos_destroy(st);
+        return rc;
+    }
+    st->grid = std::min(n_pairs, ctx->num_cus * std::max(1, std::min(per_cu, 2)));
     if ((rc = bos_alloc(st, sizeof(double) * (size_t)st->grid * NT * C, (void**)&d.qbuf))) {
         bos_destroy(st);
         return rc;
     }
     hipError_t e = hipMemcpyAsync(st->boxes, st->hb.data(), sizeof(Box) * 2 * np, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(st->ints, 0, sizeof(int) * (np * 20 + 8), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st->ints, hints.data(), sizeof(int) * hints.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st->lists, hl.data(), sizeof(int) * hl.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(st->prior, 0xff, sizeof(float) * np * 6, s);  // -nan: no prior
-    if (e == hipSuccess) e = hipFuncSetAttribute(bos_kernel_for(st->kp1), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)st->lds_bytes);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         bos_destroy(st);
         return fail(CORR_EHIP, std::string("bos_create: ") + hipGetErrorString(e));
     }
+    // the host buffers above are released on return: wait for the copies
+    if ((rc = wait_deadline(s, st->timeout_s, "bos_create"))) {
+        bos_destroy(st);
+        return rc;
+    }
     *out = st;
+    return CORR_OK;
+}
+
+int bos_set_launch(bos_state* st, int32_t mode, double timeout_s) {
+    if (!st) return fail(CORR_EINVAL, "bos_set_launch: null state");
+    if (mode != BOS_LAUNCH_GRAPH && mode != BOS_LAUNCH_PLAIN) return fail(CORR_EINVAL, "bos_set_launch: mode");
+    if (!(timeout_s > 0.0)) return fail(CORR_EINVAL, "bos_set_launch: timeout must be positive");
+    st->mode = mode;
+    st->timeout_s = timeout_s;
     return CORR_OK;
 }
 
@@ -889,8 +1015,8 @@ int bos_set_prior(bos_state* st, const float* cells) {
 }
 
 static int bos_capture(bos_state* st) {
+    if (!st->cap) CORR_HIP(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
     CORR_HIP(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
-    bos_reset_kernel<<<1, 64, 0, st->cap>>>(st->d.work, st->d.n_active);
     bos_launch_kernel(st, st->cap);
     bos_advance_kernel<<<1, 64, 0, st->cap>>>(st->d.iter);
     hipGraph_t g = nullptr;
@@ -904,34 +1030,40 @@ static int bos_capture(bos_state* st) {
 int bos_sample_step(bos_state* st, corr_stream_t stream, int32_t* n_active_out) {
     if (!st) return fail(CORR_EINVAL, "bos_sample_step: null state");
     hipStream_t s = (hipStream_t)stream;
-    if (!st->exec) {
-        int rc = bos_capture(st);
-        if (rc) return rc;
-    }
     if (st->done) {
         if (n_active_out) *n_active_out = 0;
         return CORR_OK;
     }
-    CORR_HIP(hipGraphLaunch(st->exec, s));
-    st->steps += 1;
-    if (n_active_out) {
-        int h = 0;
-        CORR_HIP(hipMemcpyAsync(&h, st->d.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-        CORR_HIP(hipStreamSynchronize(s));
-        *n_active_out = h;
-        if (h == 0) st->done = true;
+    if (st->mode == BOS_LAUNCH_GRAPH) {
+        if (!st->exec) {
+            int rc = bos_capture(st);
+            if (rc) return rc;
+        }
+        CORR_HIP(hipGraphLaunch(st->exec, s));
+    } else {
+        bos_launch_kernel(st, s);
+        CORR_LAUNCH_CHECK();
+        bos_advance_kernel<<<1, 64, 0, s>>>(st->d.iter);
+        CORR_LAUNCH_CHECK();
     }
+    st->last = s;
+    // pairs with batches left after this iteration (known from the schedule)
+    const int it = st->steps;
+    st->steps += 1;
+    int active = 0;
+    for (int p = 0; p < st->n_pairs; ++p) active += st->h_nsched[p] > it ? 1 : 0;
+    if (active == 0 || st->steps >= st->n_iter) st->done = true;
+    if (n_active_out) *n_active_out = st->done ? 0 : active;
     return CORR_OK;
 }
 
 int bos_run(bos_state* st, corr_stream_t stream) {
     if (!st) return fail(CORR_EINVAL, "bos_run: null state");
-    int32_t active = 1;
-    for (int guard = 0; guard < 64 && active > 0; ++guard) {
-        int rc = bos_sample_step(st, stream, &active);
+    while (!st->done) {
+        int rc = bos_sample_step(st, stream, nullptr);
         if (rc) return rc;
     }
-    return CORR_OK;
+    return wait_deadline((hipStream_t)stream, st->timeout_s, "bos_run");
 }
 
 int bos_results(bos_state* st, corr_max* out, corr_stream_t stream) {
@@ -939,15 +1071,17 @@ int bos_results(bos_state* st, corr_max* out, corr_stream_t stream) {
     hipStream_t s = (hipStream_t)stream;
     const size_t np = (size_t)st->n_pairs;
     const int NT = st->cfg.n_total;
-    std::vector<int> ints(np * 20 + 8);
+    std::vector<int> ints(ints_count(np));
     std::vector<int16_t> cells(np * NT * 6);
     std::vector<double> yv(np * NT);
     std::vector<float> sv(np * NT);
+    int rc = wait_deadline(s, st->timeout_s, "bos_results");
+    if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(ints.data(), st->ints, sizeof(int) * ints.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(cells.data(), st->cells, sizeof(int16_t) * cells.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(yv.data(), st->yv, sizeof(double) * yv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(sv.data(), st->sv, sizeof(float) * sv.size(), hipMemcpyDeviceToHost, s));
-    CORR_HIP(hipStreamSynchronize(s));
+    if ((rc = wait_deadline(s, st->timeout_s, "bos_results"))) return rc;
     for (size_t p = 0; p < np; ++p) {
         const int n = ints[p], b = ints[2 * np + p];
         corr_max& o = out[p];
@@ -975,38 +1109,42 @@ int bos_history(bos_state* st, int32_t pair, int32_t* cells, float* values, int3
     if (pair < 0 || pair >= st->n_pairs) return fail(CORR_EINVAL, "bos_history: pair out of range");
     hipStream_t s = (hipStream_t)stream;
     const int NT = st->cfg.n_total;
-    int n = 0;
+    std::vector<int> n(1, 0);
     std::vector<int16_t> c(NT * 6);
     std::vector<double> y(NT);
-    CORR_HIP(hipMemcpyAsync(&n, st->ints + pair, sizeof(int), hipMemcpyDeviceToHost, s));
+    int rc = wait_deadline(s, st->timeout_s, "bos_history");
+    if (rc) return rc;
+    CORR_HIP(hipMemcpyAsync(n.data(), st->ints + pair, sizeof(int), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(c.data(), st->cells + (size_t)pair * NT * 6, sizeof(int16_t) * NT * 6,
                             hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(y.data(), st->yv + (size_t)pair * NT, sizeof(double) * NT, hipMemcpyDeviceToHost, s));
-    CORR_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < n; ++i) {
+    if ((rc = wait_deadline(s, st->timeout_s, "bos_history"))) return rc;
+    for (int i = 0; i < n[0]; ++i) {
         for (int a = 0; a < 6; ++a) cells[6 * i + a] = c[6 * i + a];
         values[i] = (float)y[i];
     }
-    *n_out = n;
+    *n_out = n[0];
     return CORR_OK;
 }
 
-static const char kBosMagic[8] = {'B', 'O', 'S', 'S', 'T', 'A', 'T', '1'};
+static const char kBosMagic[8] = {'B', 'O', 'S', 'S', 'T', 'A', 'T', '2'};
 
 int bos_save(bos_state* st, const char* path, corr_stream_t stream) {
     if (!st || !path) return fail(CORR_EINVAL, "bos_save: null argument");
     hipStream_t s = (hipStream_t)stream;
     const size_t np = (size_t)st->n_pairs, NT = (size_t)st->cfg.n_total;
-    std::vector<int> ints(np * 20 + 8);
+    std::vector<int> ints(ints_count(np));
     std::vector<int16_t> cells(np * NT * 6);
     std::vector<double> yv(np * NT);
     std::vector<float> sv(np * NT), prior(np * 6);
+    int rc = wait_deadline(s, st->timeout_s, "bos_save");
+    if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(ints.data(), st->ints, sizeof(int) * ints.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(cells.data(), st->cells, sizeof(int16_t) * cells.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(yv.data(), st->yv, sizeof(double) * yv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(sv.data(), st->sv, sizeof(float) * sv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(prior.data(), st->prior, sizeof(float) * prior.size(), hipMemcpyDeviceToHost, s));
-    CORR_HIP(hipStreamSynchronize(s));
+    if ((rc = wait_deadline(s, st->timeout_s, "bos_save"))) return rc;
     FILE* f = fopen(path, "wb");
     if (!f) return fail(CORR_EINVAL, std::string("bos_save: cannot write ") + path);
     bool ok = fwrite(kBosMagic, 1, 8, f) == 8;
@@ -1037,7 +1175,7 @@ int bos_load(bos_state* st, const char* path, corr_stream_t stream) {
     bos_config cfg;
     int n_pairs = 0, M = 0, steps = 0, has_prior = 0, done = 0;
     std::vector<Box> hb(st->hb.size());
-    std::vector<int> ints(np * 20 + 8);
+    std::vector<int> ints(ints_count(np));
     std::vector<int16_t> cells(np * NT * 6);
     std::vector<double> yv(np * NT);
     std::vector<float> sv(np * NT), prior(np * 6);
@@ -1054,14 +1192,18 @@ int bos_load(bos_state* st, const char* path, corr_stream_t stream) {
     ok = ok && fread(yv.data(), sizeof(double), yv.size(), f) == yv.size();
     ok = ok && fread(sv.data(), sizeof(float), sv.size(), f) == sv.size();
     ok = ok && fread(prior.data(), sizeof(float), prior.size(), f) == prior.size();
+    ok = ok && steps >= 0 && steps <= st->n_iter && ints[20 * np] == steps;
     fclose(f);
     if (!ok) return fail(CORR_EINVAL, std::string("bos_load: file does not match this sampler: ") + path);
+    int rc = wait_deadline(s, st->timeout_s, "bos_load");
+    if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(st->ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->cells, cells.data(), sizeof(int16_t) * cells.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->yv, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->sv, sv.data(), sizeof(float) * sv.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->prior, prior.data(), sizeof(float) * prior.size(), hipMemcpyHostToDevice, s));
-    CORR_HIP(hipStreamSynchronize(s));
+    if ((rc = wait_deadline(s, st->timeout_s, "bos_load"))) return rc;
+    st->last = s;
     st->steps = steps;
     st->done = done != 0;
     st->d.prior = has_prior ? st->prior : nullptr;

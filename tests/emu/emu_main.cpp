@@ -101,6 +101,10 @@ int launch_transpose(const corr_field& f, const Box& box, Stats st, int fmt, voi
         }
     return 0;
 }
+int kernel_setup(const void*, size_t, int, int* per_cu) {
+    if (per_cu) *per_cu = 1;
+    return 0;
+}
 int launch_sort_rows(const float* z, int64_t ld, int64_t nrows, int M, float* out, int, hipStream_t) {
     int p2 = ksg_p2(M);
     for (int64_t r = 0; r < nrows; ++r) {
@@ -151,6 +155,8 @@ int main(int argc, char** argv) {
     bos_state* st = nullptr;
     int rc = bos_create(&ctx, &f, &f, rr.data(), nr, pairs, np, &cfg, &st, nullptr);
     std::fprintf(stderr, "bos_create rc=%d launches=%ld\n", rc, emu_launches);
+    if (rc) return 1;
+    if (argc > 3 && std::string(argv[3]) == "plain") rc = bos_set_launch(st, BOS_LAUNCH_PLAIN, 60.0);
     if (rc) return 1;
     for (int s = 0; s < 64; ++s) {
         int32_t act = -1;

@@ -69,15 +69,27 @@ inline float emu_fmed3f(float a, float b, float c) { return std::fmax(std::fmin(
 #define __builtin_amdgcn_fmed3f emu_fmed3f
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 #define __builtin_amdgcn_wave_barrier() emu_wave_sync()
+// readfirstlane: the value of the wave's first lane (lane 0 is always active
+// where the kernels use it; a differing value would be a kernel bug)
+inline int emu_readfirstlane(int v) {
+    const int r = emu_shfl(v, 0);
+    if (r != v) {
+        std::fprintf(stderr, "readfirstlane of a non-uniform value\n");
+        std::abort();
+    }
+    return r;
+}
+#define __builtin_amdgcn_readfirstlane emu_readfirstlane
 
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorNotReady = 600 };
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
 typedef struct EmuGraph* hipGraph_t;
 typedef struct EmuGraph* hipGraphExec_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyHostToHost };
-enum { hipStreamNonBlocking = 1, hipStreamCaptureModeThreadLocal = 1, hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
+enum { hipStreamNonBlocking = 1, hipStreamCaptureModeThreadLocal = 1, hipFuncAttributeMaxDynamicSharedMemorySize = 8,
+       hipEventDisableTiming = 2 };
 typedef int hipStreamCaptureMode;
 
 struct EmuGraph {
@@ -116,6 +128,11 @@ inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = emu_gra
 inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void*, void*, size_t) { *e = g; return hipSuccess; }
 inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) { for (auto& n : e->nodes) n(); return hipSuccess; }
 inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+// launches run to completion when enqueued, so an event is complete at once
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = std::malloc(1); return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventQuery(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSuccess; }
 inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
 struct alignas(8) float2 { float x, y; };
 struct alignas(16) float4 { float x, y, z, w; };

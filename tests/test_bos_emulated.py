@@ -44,17 +44,17 @@ def emu_bin(tmp_path_factory):
     return exe, d
 
 
-def _run(emu_bin, e, pairs, measure, seed):
+def _run(emu_bin, e, pairs, measure, seed, mode="graph"):
     exe, d = emu_bin
-    inp = os.path.join(d, f"in_{measure}_{seed}.bin")
-    out = os.path.join(d, f"out_{measure}_{seed}.txt")
+    inp = os.path.join(d, f"in_{measure}_{seed}_{mode}.bin")
+    out = os.path.join(d, f"out_{measure}_{seed}_{mode}.txt")
     hdr = np.array([e.M, e.nx, e.ny, e.nz, len(e.regions), len(pairs), 0 if measure == "pearson" else 1, seed],
                    np.int32)
     regs = np.array([r.as_tuple() for r in e.regions], np.int32)
     with open(inp, "wb") as fh:
         for a in (hdr, np.ascontiguousarray(e.data, np.float32), regs, np.asarray(pairs, np.int32)):
             fh.write(a.tobytes())
-    r = subprocess.run([exe, inp, out], capture_output=True, text=True, timeout=600)
+    r = subprocess.run([exe, inp, out, mode], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "ERROR: AddressSanitizer" not in r.stderr
     hist, lines, i = {}, open(out).read().split("\n"), 0
@@ -67,11 +67,12 @@ def _run(emu_bin, e, pairs, measure, seed):
     return hist, r.stderr
 
 
-@pytest.mark.parametrize("measure,npairs,seed", [("pearson", 6, 3), ("ksg", 2, 4)])
-def test_emulated_bos_matches_oracle(emu_bin, measure, npairs, seed):
+@pytest.mark.parametrize("measure,npairs,seed,mode", [("pearson", 6, 3, "graph"), ("pearson", 5, 3, "plain"),
+                                                    ("ksg", 2, 4, "graph")])
+def test_emulated_bos_matches_oracle(emu_bin, measure, npairs, seed, mode):
     e = synth.make_context(4, 2, (12, 12, 6), M=100, seed=21, n_groups=3, blob_r=2.0, min_region_gap=2)
     pairs = synth.region_pair_list(len(e.regions))[:npairs]
-    hist, log = _run(emu_bin, e, pairs, measure, seed)
+    hist, log = _run(emu_bin, e, pairs, measure, seed, mode)
     assert "active=0" in log
     cfg = B.BosConfig(seed=seed)
     for p, (ia, ib) in enumerate(pairs):

@@ -3,6 +3,9 @@
 Step parity: the oracle replays every pair's GPU history batch by batch and
 must reproduce the cells the GPU chose (same candidates, believer picks,
 rounding and dedupe). Objective values match the oracle's Pearson / KSG.
+Direct launches and the captured-graph launches give bit-identical
+histories. Every library wait is bounded (bos_set_launch), so a kernel that
+did not finish would fail the test instead of blocking it.
 """
 import os
 import sys
@@ -15,12 +18,10 @@ import synth
 from oracle import bos_ref as B
 from test_oracle_bos import replay_iterations
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="the first BOS create/step stalled for more than 3 minutes on the MI355X (the run was "
-                            "killed; the GPU stayed responsive) and the cause is not identified yet; the kernel logic "
-                            "is checked on the CPU by tests/test_bos_emulated.py"),
-]
+pytestmark = pytest.mark.gpu
+
+# every wait of the library for the GPU gives up after this many seconds
+TIMEOUT_S = 60.0
 
 
 def _say(msg):
@@ -78,10 +79,40 @@ def _check_history(env, bos, measure, pairs_to_check):
     return full, res
 
 
+def _bos(env, cfg, pairs=None, mode="graph"):
+    pc = env["pc"]
+    b = pc.Bos(env["ctx"], env["f"], env["regions"], env["pairs"] if pairs is None else pairs, cfg)
+    b.bos_set_launch(mode, TIMEOUT_S)
+    return b
+
+
+def _histories(bos, n):
+    return [bos.bos_history(p) for p in range(n)]
+
+
+def test_bos_pearson_plain_launch_matches_oracle_replay(env):
+    pc = env["pc"]
+    _say(f"  pearson BOS (direct launches) over {len(env['pairs'])} pairs: create")
+    bos = _bos(env, pc.bos_defaults(seed=3), mode="plain")
+    steps = 0
+    for _ in range(64):
+        active = bos.bos_sample_step()
+        steps += 1
+        _say(f"  step {steps}: {active} pairs active")
+        if active == 0:
+            break
+    assert active == 0 and steps <= 12
+    full, res = _check_history(env, bos, "pearson", range(len(env["pairs"])))
+    _say(f"  batches reproduced exactly for {full}/{len(env['pairs'])} pairs")
+    assert full >= 0.9 * len(env["pairs"])
+    env["plain_hist"] = _histories(bos, len(env["pairs"]))
+    bos.close()
+
+
 def test_bos_pearson_matches_oracle_replay(env):
     pc, ctx, f = env["pc"], env["ctx"], env["f"]
-    _say(f"  pearson BOS over {len(env['pairs'])} pairs: create")
-    bos = pc.Bos(ctx, f, env["regions"], env["pairs"], pc.bos_defaults(seed=3))
+    _say(f"  pearson BOS (graph) over {len(env['pairs'])} pairs: create")
+    bos = _bos(env, pc.bos_defaults(seed=3))
     steps = 0
     for _ in range(64):  # at most 1 + 80 / 8 iterations are ever active
         active = bos.bos_sample_step()
@@ -93,6 +124,9 @@ def test_bos_pearson_matches_oracle_replay(env):
     full, res = _check_history(env, bos, "pearson", range(len(env["pairs"])))
     _say(f"  batches reproduced exactly for {full}/{len(env['pairs'])} pairs")
     assert full >= 0.9 * len(env["pairs"])
+    if "plain_hist" in env:  # the captured graph replays exactly the direct launches
+        for (c0, v0), (c1, v1) in zip(env["plain_hist"], _histories(bos, len(env["pairs"]))):
+            assert np.array_equal(c0, c1) and np.array_equal(v0, v1)
     # never above the exhaustive maximum
     for p, (ia, ib) in enumerate(env["pairs"]):
         ex = ctx.corr_region_max(f, env["regions"][ia], env["regions"][ib], "pearson", "f32")
@@ -103,7 +137,8 @@ def test_bos_pearson_matches_oracle_replay(env):
 def test_bos_ksg_matches_oracle_replay(env):
     pc, ctx, f = env["pc"], env["ctx"], env["f"]
     sub = env["pairs"][:6]
-    bos = pc.Bos(ctx, f, env["regions"], sub, pc.bos_defaults(measure="ksg", k=10, seed=4))
+    _say("  ksg BOS over 6 pairs")
+    bos = _bos(env, pc.bos_defaults(measure="ksg", k=10, seed=4), pairs=sub)
     bos.bos_run()
     env2 = dict(env, pairs=sub)
     full, _ = _check_history(env2, bos, "ksg", range(len(sub)))
@@ -114,17 +149,18 @@ def test_bos_ksg_matches_oracle_replay(env):
 def test_bos_determinism_save_load(env, tmp_path):
     pc, ctx, f = env["pc"], env["ctx"], env["f"]
     cfg = pc.bos_defaults(seed=9)
-    a = pc.Bos(ctx, f, env["regions"], env["pairs"], cfg)
+    _say("  BOS save / load")
+    a = _bos(env, cfg)
     a.bos_run()
     ra = a.bos_results()
-    b = pc.Bos(ctx, f, env["regions"], env["pairs"], cfg)
+    b = _bos(env, cfg)
     b.bos_sample_step()
     b.bos_sample_step()
     path = os.path.join(str(tmp_path), "bos.state")
     b.bos_save(path)
     b.bos_run()
     assert b.bos_results() == ra
-    c = pc.Bos(ctx, f, env["regions"], env["pairs"], cfg)
+    c = _bos(env, cfg, mode="plain")
     c.bos_load(path)
     c.bos_run()
     assert c.bos_results() == ra
@@ -147,7 +183,8 @@ def test_bos_prior_cell_is_evaluated_first(env):
         cb = ((ex["pb"] % e.nx) - rb.x0, (ex["pb"] // e.nx % e.ny) - rb.y0, (ex["pb"] // (e.nx * e.ny)) - rb.z0)
         prior[p] = ca + cb
         truth.append(ex["value"])
-    bos = pc.Bos(ctx, f, env["regions"], pairs, pc.bos_defaults(seed=5, n_total=28))
+    _say("  BOS with a prior cell")
+    bos = _bos(env, pc.bos_defaults(seed=5, n_total=28))
     bos.bos_set_prior(prior)
     bos.bos_run()
     res = bos.bos_results()
@@ -166,3 +203,12 @@ def test_bos_error_paths(env):
         pc.Bos(ctx, f, env["regions"], env["pairs"], pc.bos_defaults(n_total=101))
     with pytest.raises(pc.CorrError):
         pc.Bos(ctx, f, env["regions"], env["pairs"], pc.bos_defaults(n_uniform=10, n_local=10))
+    b = _bos(env, pc.bos_defaults(n_total=28))
+    with pytest.raises(pc.CorrError):
+        b.bos_set_launch("plain", 0.0)
+    b.bos_sample_step()
+    with pytest.raises(pc.CorrError):  # the prior must come before sampling
+        b.bos_set_prior(np.zeros((len(env["pairs"]), 6), np.float32))
+    b.bos_run()
+    assert b.bos_sample_step() == 0  # done: further steps do nothing
+    b.close()

@@ -160,3 +160,88 @@ def test_replay_reproduces_an_oracle_run():
         res = B.run_pair(cfg, pair, dims, f)
         m, t = replay_iterations(cfg, pair, dims, res["cells"], res["values"])
         assert m == t
+
+
+def _numpy_word0(seed, pair, stream, index, axis):
+    """Word 0 of the Philox4x64-10 block at counter (pair, stream, index, axis)
+    under key (seed, 0x636f7272), from numpy's generator (it adds one to the
+    counter before its first block, so it starts one below)."""
+    ctr = (pair | (stream << 64) | (index << 128) | (axis << 192)) - 1  # 256-bit counter, word 0 lowest
+    if ctr < 0:
+        ctr += 1 << 256
+    words = [(ctr >> (64 * i)) & ((1 << 64) - 1) for i in range(4)]
+    bg = np.random.Philox(key=np.array([seed, B.KEY_HI], np.uint64), counter=np.array(words, np.uint64))
+    return int(bg.random_raw(1)[0])
+
+
+def test_initial_design_is_floor_of_u_times_d_from_numpy_philox():
+    # Sec. 3.1 initial design: every coordinate floor(u * d) with u the top
+    # 53 bits of Philox word 0 (numpy's generator as the reference stream)
+    cfg = B.BosConfig(seed=31)
+    dims = (32, 32, 20, 7, 1, 13)
+    for pair in (0, 1, 17, 3827):
+        got = B.initial_cells(cfg, pair, dims)
+        for s in range(cfg.n_init):
+            for a in range(6):
+                u = (_numpy_word0(cfg.seed, pair, B.S_INIT, s, a) >> 11) / 2.0 ** 53
+                assert got[s, a] == min(int(np.floor(u * dims[a])), dims[a] - 1)
+    assert (B.initial_cells(cfg, 5, dims)[:, 4] == 0).all()  # a one-cell axis
+
+
+def test_uniform_candidates_are_uniform_on_zero_to_d_minus_one():
+    from scipy import stats
+    cfg = B.BosConfig(seed=12, n_uniform=1024, n_local=0)
+    dims = (32, 9, 20, 32, 2, 20)
+    th = np.vstack([B.candidates(cfg, 4, it, dims, np.zeros(6)) for it in range(4)])
+    for a in range(6):
+        up = dims[a] - 1
+        assert th[:, a].min() >= 0.0 and th[:, a].max() <= up
+        # Kolmogorov-Smirnov against U(0, d - 1): scaling by d instead of
+        # d - 1 moves the CDF by up to 1/d and fails at these sample sizes
+        p = stats.kstest(th[:, a], stats.uniform(loc=0.0, scale=up).cdf).pvalue
+        assert p > 1e-3, (a, p)
+    # the exact draw: word 0 of stream 2 at index it * n_uniform + c
+    u = (_numpy_word0(cfg.seed, 4, B.S_UNIF, 2 * 1024 + 5, 3) >> 11) / 2.0 ** 53
+    assert th[2 * 1024 + 5, 3] == u * (dims[3] - 1)
+
+
+def test_local_candidates_are_normal_around_the_incumbent_before_clipping():
+    from scipy import stats
+    sd = 1.7
+    cfg = B.BosConfig(seed=14, n_uniform=0, n_local=1024, local_sd=sd)
+    dims = (200, 200, 200, 200, 200, 200)
+    best = np.array([100.0, 50.0, 150.0, 99.0, 120.0, 60.0])  # far from the faces: no clipping
+    th = np.vstack([B.candidates(cfg, 9, it, dims, best) for it in range(3)])
+    for a in range(6):
+        p = stats.kstest(th[:, a], stats.norm(loc=best[a], scale=sd).cdf).pvalue
+        assert p > 1e-3, (a, p)
+    # clipping to the box at a face
+    th = B.candidates(B.BosConfig(seed=14, n_uniform=0, n_local=256, local_sd=sd), 9, 0, (8,) * 6, np.zeros(6))
+    assert th.min() == 0.0 and (th == 0.0).mean() > 0.3 and th.max() <= 7.0
+
+
+def test_duplicate_cells_are_dropped_but_use_their_slots():
+    # a 2-cell domain: after the initial design every rounded pick is a
+    # repeat; none is evaluated again, and every batch still advances the
+    # rounding stream by its full size
+    cfg = B.BosConfig(seed=23)
+    dims = (1, 1, 1, 1, 1, 2)
+    calls = []
+
+    def f(c):
+        calls.append(np.asarray(c).copy())
+        return np.asarray(c, float)[:, 5] + 0.5
+
+    res = B.run_pair(cfg, 0, dims, f)
+    assert res["n_evaluated"] == 2 and sum(len(c) for c in calls) == 2
+    assert {tuple(c) for c in res["cells"]} == {(0, 0, 0, 0, 0, 0), (0, 0, 0, 0, 0, 1)}
+    # rounding of batch 1 draws from slot n_init + b_0
+    sched = B.schedule(cfg, 0)
+    X = res["cells"]
+    slot = cfg.n_init + sched[0]
+    theta = np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.4])
+    cell = B.round_cell(cfg, 0, slot, theta, dims)
+    u = (_numpy_word0(cfg.seed, 0, B.S_ROUND, slot, 5) >> 11) / 2.0 ** 53
+    assert cell[5] == (1 if u < 0.4 else 0)
+    new, b = B.iteration_cells(cfg, 0, 1, dims, X, res["values"], slot)
+    assert b == sched[1] and new.shape[0] == 0
