@@ -89,6 +89,8 @@ struct BosDev {
     const int* list_start;    // [n_iter] offset of iteration t's pairs in list
     const int* list_count;    // [n_iter] number of pairs sampling in iteration t
     int n_iter;               // iterations listed (initial design included)
+    int* err;                 // bit 0: inconsistent pair state, bit 1: stopped by the host
+    const int* stop;          // host-mapped: nonzero asks every workgroup to stop at its next pair
     double* qbuf;  // per workgroup [n_total][C]
     // LDS layout (in doubles)
     int off_L, off_X, off_y, off_a, off_th, off_mu, off_s2, off_qs, off_pk, off_red, off_misc, lds_doubles;
@@ -332,6 +334,12 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = uni(d.n_obs[pair]);
     const int b = uni(d.sched[pair * 16 + t]);
+    // every loop below is bounded by n, b and C; state that could not have
+    // been written by this sampler is flagged rather than followed
+    if (n < 1 || b < 1 || b > 64 || n + b > d.n_total) {
+        if (tid == 0) atomicOr(d.err, 1);
+        return;
+    }
     const int C = d.C;
     const int base = pair * d.n_total;
     double* L = sm + d.off_L;
@@ -572,7 +580,15 @@ __global__ __launch_bounds__(256) void bos_kernel(BosDev d) {
     const int start = uni(d.list_start[it]), count = uni(d.list_count[it]);
     // static stride over the iteration's pairs: at most ceil(count / grid) trips
     for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        if (uni(__hip_atomic_load(d.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0) {
+            if (threadIdx.x == 0) atomicOr(d.err, 2);
+            break;
+        }
         const int pair = uni(d.list[start + q]);
+        if (pair < 0 || pair >= d.n_pairs) {
+            if (threadIdx.x == 0) atomicOr(d.err, 1);
+            break;
+        }
         if (it == 0)
             bos_init_pair<KP1>(d, pair, sm);
         else
@@ -605,6 +621,7 @@ struct bos_state {
     int* lists = nullptr;  // list_start[n_iter], list_count[n_iter], list[]
     float* prior = nullptr;
     Box* boxes = nullptr;  // [2][n_pairs]
+    int* h_stop = nullptr;  // pinned, mapped: the kernels' stop request
     std::vector<Box> hb;   // host copy of the pair boxes
     std::vector<int> h_nsched, h_sched;  // host copy of the schedule
     int n_iter = 0;
@@ -618,7 +635,9 @@ struct bos_state {
     bool used = false;
     int steps = 0;
     bool done = false;
+    bool stopped = false;  // a wait passed its deadline: no further work is accepted
 };
+
 
 static size_t ints_count(size_t np) { return np * 20 + 8; }
 
@@ -633,8 +652,10 @@ static int bos_alloc(bos_state* st, size_t bytes, void** p) {
 }
 
 // Wait for the work enqueued on `s` so far, polling an event, and give up with
-// CORR_EHIP after `timeout_s` seconds instead of blocking without bound.
-static int wait_deadline(hipStream_t s, double timeout_s, const char* what) {
+// CORR_EHIP after `timeout_s` seconds instead of blocking without bound. With
+// a stop flag, a wait that passes its deadline asks the BOS kernels to stop at
+// their next pair and waits up to another 10 s for them to drain.
+static int wait_deadline(hipStream_t s, double timeout_s, const char* what, volatile int* stop = nullptr) {
     hipEvent_t ev = nullptr;
     CORR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     hipError_t e = hipEventRecord(ev, s);
@@ -642,7 +663,8 @@ static int wait_deadline(hipStream_t s, double timeout_s, const char* what) {
         (void)hipEventDestroy(ev);
         return fail(CORR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
     }
-    const auto t0 = std::chrono::steady_clock::now();
+    auto t0 = std::chrono::steady_clock::now();
+    bool stopping = false;
     for (;;) {
         e = hipEventQuery(ev);
         if (e == hipSuccess) break;
@@ -651,15 +673,32 @@ static int wait_deadline(hipStream_t s, double timeout_s, const char* what) {
             return fail(CORR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
         }
         const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (dt > timeout_s) {
+        if (!stopping && dt > timeout_s && stop) {
+            *stop = 1;
+            stopping = true;
+            t0 = std::chrono::steady_clock::now();
+            continue;
+        }
+        if ((!stopping && dt > timeout_s) || (stopping && dt > 10.0)) {
             (void)hipEventDestroy(ev);
             return fail(CORR_EHIP, std::string(what) + ": the GPU work did not finish within " +
-                                       std::to_string(timeout_s) + " s");
+                                       std::to_string(timeout_s) + " s" +
+                                       (stopping ? " and did not stop on request" : ""));
         }
         std::this_thread::sleep_for(std::chrono::microseconds(dt < 0.01 ? 20 : 500));
     }
     (void)hipEventDestroy(ev);
+    if (stopping)
+        return fail(CORR_EHIP, std::string(what) + ": the GPU work did not finish within " +
+                                   std::to_string(timeout_s) + " s; it was stopped (the sampler's results are incomplete)");
     return CORR_OK;
+}
+
+// Wait with the sampler's deadline; a stop by deadline poisons the sampler.
+static int bos_wait(bos_state* st, hipStream_t s, const char* what) {
+    const int rc = wait_deadline(s, st->timeout_s, what, st->h_stop);
+    if (rc && st->h_stop && *(volatile int*)st->h_stop) st->stopped = true;
+    return rc;
 }
 
 // Standardise a whole field into state-owned buffers: rows (format fmt,
@@ -786,11 +825,12 @@ void bos_destroy(bos_state* st) {
     if (!st) return;
     // never free memory that enqueued work may still use: if that work does
     // not finish in time the buffers are left allocated
-    if (st->used && wait_deadline(st->last, st->timeout_s, "bos_destroy") != CORR_OK) return;
+    if (st->used && bos_wait(st, st->last, "bos_destroy") != CORR_OK && !st->stopped) return;
     if (st->exec) (void)hipGraphExecDestroy(st->exec);
     if (st->graph) (void)hipGraphDestroy(st->graph);
     if (st->cap) (void)hipStreamDestroy(st->cap);
     for (void* p : st->allocs) (void)hipFree(p);
+    if (st->h_stop) (void)hipHostFree(st->h_stop);
     delete st;
 }
 
@@ -916,6 +956,21 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     if (!rc) rc = bos_alloc(st, sizeof(int) * hl.size(), (void**)&st->lists);
     if (!rc) rc = bos_alloc(st, sizeof(float) * np * 6, (void**)&st->prior);
     if (!rc) rc = bos_alloc(st, sizeof(Box) * 2 * np, (void**)&st->boxes);
+    if (!rc) {
+        void* dstop = nullptr;
+        hipError_t he = hipHostMalloc((void**)&st->h_stop, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
+        if (he == hipSuccess) {
+            *(volatile int*)st->h_stop = 0;
+            he = hipHostGetDevicePointer(&dstop, st->h_stop, 0);
+        } else {
+            st->h_stop = nullptr;
+        }
+        if (he != hipSuccess) {
+            (void)hipGetLastError();
+            rc = fail(CORR_ENOMEM, std::string("bos_create: pinned stop flag: ") + hipGetErrorString(he));
+        }
+        d.stop = (const int*)dstop;
+    }
     if (rc) {
         bos_destroy(st);
         return rc;
@@ -929,6 +984,7 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     d.n_sched = st->ints + 3 * np;
     d.sched = st->ints + 4 * np;  // [np][16]
     d.iter = st->ints + 20 * np;
+    d.err = st->ints + 20 * np + 1;
     d.n_iter = st->n_iter;
     d.list_start = st->lists;
     d.list_count = st->lists + st->n_iter;
@@ -983,7 +1039,7 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
         return fail(CORR_EHIP, std::string("bos_create: ") + hipGetErrorString(e));
     }
     // the host buffers above are released on return: wait for the copies
-    if ((rc = wait_deadline(s, st->timeout_s, "bos_create"))) {
+    if ((rc = bos_wait(st, s, "bos_create"))) {
         bos_destroy(st);
         return rc;
     }
@@ -1029,6 +1085,7 @@ static int bos_capture(bos_state* st) {
 
 int bos_sample_step(bos_state* st, corr_stream_t stream, int32_t* n_active_out) {
     if (!st) return fail(CORR_EINVAL, "bos_sample_step: null state");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_sample_step: the sampler was stopped after a deadline passed");
     hipStream_t s = (hipStream_t)stream;
     if (st->done) {
         if (n_active_out) *n_active_out = 0;
@@ -1059,15 +1116,17 @@ int bos_sample_step(bos_state* st, corr_stream_t stream, int32_t* n_active_out) 
 
 int bos_run(bos_state* st, corr_stream_t stream) {
     if (!st) return fail(CORR_EINVAL, "bos_run: null state");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_run: the sampler was stopped after a deadline passed");
     while (!st->done) {
         int rc = bos_sample_step(st, stream, nullptr);
         if (rc) return rc;
     }
-    return wait_deadline((hipStream_t)stream, st->timeout_s, "bos_run");
+    return bos_wait(st, (hipStream_t)stream, "bos_run");
 }
 
 int bos_results(bos_state* st, corr_max* out, corr_stream_t stream) {
     if (!st || !out) return fail(CORR_EINVAL, "bos_results: null argument");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_results: the sampler was stopped after a deadline passed");
     hipStream_t s = (hipStream_t)stream;
     const size_t np = (size_t)st->n_pairs;
     const int NT = st->cfg.n_total;
@@ -1075,13 +1134,15 @@ int bos_results(bos_state* st, corr_max* out, corr_stream_t stream) {
     std::vector<int16_t> cells(np * NT * 6);
     std::vector<double> yv(np * NT);
     std::vector<float> sv(np * NT);
-    int rc = wait_deadline(s, st->timeout_s, "bos_results");
+    int rc = bos_wait(st, s, "bos_results");
     if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(ints.data(), st->ints, sizeof(int) * ints.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(cells.data(), st->cells, sizeof(int16_t) * cells.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(yv.data(), st->yv, sizeof(double) * yv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(sv.data(), st->sv, sizeof(float) * sv.size(), hipMemcpyDeviceToHost, s));
-    if ((rc = wait_deadline(s, st->timeout_s, "bos_results"))) return rc;
+    if ((rc = bos_wait(st, s, "bos_results"))) return rc;
+    if (ints[20 * np + 1] & 1) return fail(CORR_ESTATE, "bos_results: the kernels found inconsistent pair state");
+    if (ints[20 * np + 1] & 2) return fail(CORR_ESTATE, "bos_results: the kernels were stopped; results are incomplete");
     for (size_t p = 0; p < np; ++p) {
         const int n = ints[p], b = ints[2 * np + p];
         corr_max& o = out[p];
@@ -1106,19 +1167,20 @@ int bos_results(bos_state* st, corr_max* out, corr_stream_t stream) {
 
 int bos_history(bos_state* st, int32_t pair, int32_t* cells, float* values, int32_t* n_out, corr_stream_t stream) {
     if (!st || !cells || !values || !n_out) return fail(CORR_EINVAL, "bos_history: null argument");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_history: the sampler was stopped after a deadline passed");
     if (pair < 0 || pair >= st->n_pairs) return fail(CORR_EINVAL, "bos_history: pair out of range");
     hipStream_t s = (hipStream_t)stream;
     const int NT = st->cfg.n_total;
     std::vector<int> n(1, 0);
     std::vector<int16_t> c(NT * 6);
     std::vector<double> y(NT);
-    int rc = wait_deadline(s, st->timeout_s, "bos_history");
+    int rc = bos_wait(st, s, "bos_history");
     if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(n.data(), st->ints + pair, sizeof(int), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(c.data(), st->cells + (size_t)pair * NT * 6, sizeof(int16_t) * NT * 6,
                             hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(y.data(), st->yv + (size_t)pair * NT, sizeof(double) * NT, hipMemcpyDeviceToHost, s));
-    if ((rc = wait_deadline(s, st->timeout_s, "bos_history"))) return rc;
+    if ((rc = bos_wait(st, s, "bos_history"))) return rc;
     for (int i = 0; i < n[0]; ++i) {
         for (int a = 0; a < 6; ++a) cells[6 * i + a] = c[6 * i + a];
         values[i] = (float)y[i];
@@ -1131,20 +1193,21 @@ static const char kBosMagic[8] = {'B', 'O', 'S', 'S', 'T', 'A', 'T', '2'};
 
 int bos_save(bos_state* st, const char* path, corr_stream_t stream) {
     if (!st || !path) return fail(CORR_EINVAL, "bos_save: null argument");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_save: the sampler was stopped after a deadline passed");
     hipStream_t s = (hipStream_t)stream;
     const size_t np = (size_t)st->n_pairs, NT = (size_t)st->cfg.n_total;
     std::vector<int> ints(ints_count(np));
     std::vector<int16_t> cells(np * NT * 6);
     std::vector<double> yv(np * NT);
     std::vector<float> sv(np * NT), prior(np * 6);
-    int rc = wait_deadline(s, st->timeout_s, "bos_save");
+    int rc = bos_wait(st, s, "bos_save");
     if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(ints.data(), st->ints, sizeof(int) * ints.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(cells.data(), st->cells, sizeof(int16_t) * cells.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(yv.data(), st->yv, sizeof(double) * yv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(sv.data(), st->sv, sizeof(float) * sv.size(), hipMemcpyDeviceToHost, s));
     CORR_HIP(hipMemcpyAsync(prior.data(), st->prior, sizeof(float) * prior.size(), hipMemcpyDeviceToHost, s));
-    if ((rc = wait_deadline(s, st->timeout_s, "bos_save"))) return rc;
+    if ((rc = bos_wait(st, s, "bos_save"))) return rc;
     FILE* f = fopen(path, "wb");
     if (!f) return fail(CORR_EINVAL, std::string("bos_save: cannot write ") + path);
     bool ok = fwrite(kBosMagic, 1, 8, f) == 8;
@@ -1167,6 +1230,7 @@ int bos_save(bos_state* st, const char* path, corr_stream_t stream) {
 
 int bos_load(bos_state* st, const char* path, corr_stream_t stream) {
     if (!st || !path) return fail(CORR_EINVAL, "bos_load: null argument");
+    if (st->stopped) return fail(CORR_ESTATE, "bos_load: the sampler was stopped after a deadline passed");
     hipStream_t s = (hipStream_t)stream;
     FILE* f = fopen(path, "rb");
     if (!f) return fail(CORR_EINVAL, std::string("bos_load: cannot read ") + path);
@@ -1195,14 +1259,14 @@ int bos_load(bos_state* st, const char* path, corr_stream_t stream) {
     ok = ok && steps >= 0 && steps <= st->n_iter && ints[20 * np] == steps;
     fclose(f);
     if (!ok) return fail(CORR_EINVAL, std::string("bos_load: file does not match this sampler: ") + path);
-    int rc = wait_deadline(s, st->timeout_s, "bos_load");
+    int rc = bos_wait(st, s, "bos_load");
     if (rc) return rc;
     CORR_HIP(hipMemcpyAsync(st->ints, ints.data(), sizeof(int) * ints.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->cells, cells.data(), sizeof(int16_t) * cells.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->yv, yv.data(), sizeof(double) * yv.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->sv, sv.data(), sizeof(float) * sv.size(), hipMemcpyHostToDevice, s));
     CORR_HIP(hipMemcpyAsync(st->prior, prior.data(), sizeof(float) * prior.size(), hipMemcpyHostToDevice, s));
-    if ((rc = wait_deadline(s, st->timeout_s, "bos_load"))) return rc;
+    if ((rc = bos_wait(st, s, "bos_load"))) return rc;
     st->last = s;
     st->steps = steps;
     st->done = done != 0;
