@@ -35,6 +35,7 @@
 #ifndef CORR_H
 #define CORR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -177,6 +178,28 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
 int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
                     const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
                     int64_t n_samples, corr_max* out, corr_stream_t stream);
+
+/*
+ * corr_region_max without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. Same arguments, validation, kernels and results as
+ * corr_region_max (out: HOST, the call synchronises `stream`). Its
+ * workspaces (statistics, standardised rows, sorted rows, self-pair list)
+ * come from a fixed device array of CORR_SCRATCH_BYTES per GPU, owned by the
+ * library and held until the process ends, instead of the context's
+ * grow-only buffers; the call makes no hipMalloc / hipFree or other
+ * allocating call. A call that needs more scratch returns CORR_EINVAL with
+ * the size in corr_last_error(). Every context on a GPU shares that GPU's
+ * array and it keeps the last call's contents: calls that overlap in time on
+ * one GPU (two streams, two host threads) race on it and must be ordered by
+ * the caller.
+ * Sizes: e.g. exhaustive FP16 Pearson over two 20480-point regions at M = 100
+ * needs about 10 MB; KSG over the same regions about 38 MB.
+ */
+#define CORR_SCRATCH_BYTES ((size_t)64 << 20)
+int corr_region_max_noalloc(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                            const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                            int64_t n_samples, corr_max* out, corr_stream_t stream);
 
 /*
  * Autotuner for the exhaustive Pearson contraction (tile shapes of the

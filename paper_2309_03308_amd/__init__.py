@@ -156,15 +156,22 @@ class Context:
 
     def corr_region_max(self, A: Field, ra: corr_region, rb: corr_region, measure="pearson", prec="f16", k=10,
                         B: Field = None, samples=None, stream=None) -> dict:
+        return self._region_max(self.L.corr_region_max, A, ra, rb, measure, prec, k, B, samples, stream)
+
+    def corr_region_max_noalloc(self, A: Field, ra: corr_region, rb: corr_region, measure="pearson", prec="f16",
+                                k=10, B: Field = None, samples=None, stream=None) -> dict:
+        """corr_region_max with the library's fixed per-GPU scratch (no device allocation)."""
+        return self._region_max(self.L.corr_region_max_noalloc, A, ra, rb, measure, prec, k, B, samples, stream)
+
+    def _region_max(self, fn, A, ra, rb, measure, prec, k, B, samples, stream) -> dict:
         B = A if B is None else B
         out = corr_max()
         if samples is None:
             sp, ns = None, 0
         else:
             sp, ns = _pairs_arg(samples)
-        _lib.check(self.L.corr_region_max(self.h, ctypes.byref(A.c), ctypes.byref(ra), ctypes.byref(B.c),
-                                          ctypes.byref(rb), MEASURE[measure], PREC[prec], int(k), sp, ns,
-                                          ctypes.byref(out), _stream_ptr(stream)))
+        _lib.check(fn(self.h, ctypes.byref(A.c), ctypes.byref(ra), ctypes.byref(B.c), ctypes.byref(rb),
+                      MEASURE[measure], PREC[prec], int(k), sp, ns, ctypes.byref(out), _stream_ptr(stream)))
         return dict(value=out.value, signed_value=out.signed_value, pa=out.pa, pb=out.pb,
                     n_evaluated=out.n_evaluated)
 

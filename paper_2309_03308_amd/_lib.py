@@ -68,6 +68,9 @@ SIGNATURES = {
                                _P, _P, _P]),
     "corr_region_max": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), ctypes.POINTER(corr_field),
                              ctypes.POINTER(corr_region), _I, _I, _I32, _P, _I64, ctypes.POINTER(corr_max), _P]),
+    "corr_region_max_noalloc": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region),
+                                     ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I, _I, _I32, _P, _I64,
+                                     ctypes.POINTER(corr_max), _P]),
     "corr_autotune": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), ctypes.POINTER(corr_field),
                            ctypes.POINTER(corr_region), _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float), _P]),
     "corr_ksg_autotune": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), _P, _I64, _I32, _I,

@@ -16,6 +16,32 @@ namespace corr {
 
 static thread_local std::string g_last_error;
 
+// Fixed device scratch of the no-allocation entry point: one copy per GPU,
+// held until the process ends. Host code never passes `scratch` itself to a
+// kernel (in host code the name is a host-side stand-in); it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[CORR_SCRATCH_BYTES];
+
+// The device address of `scratch` on `device` (the caller has made it
+// current), looked up once per device.
+static int scratch_address(int device, void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return fail(CORR_EHIP, std::string("scratch symbol address: ") + hipGetErrorString(e));
+        }
+        it = addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return CORR_OK;
+}
+
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 int fail(int status, const std::string& msg) {
@@ -44,6 +70,26 @@ int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out
     *out = ctx->ws[slot];
     return CORR_OK;
 }
+
+// Where a call's workspaces come from: the context's grow-only slots, or a
+// fixed arena carved front to back in 256-byte steps (the no-allocation
+// entry point), which fails with CORR_EINVAL when the call needs more.
+struct Ws {
+    corr_ctx* ctx = nullptr;
+    char* arena = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    int get(int slot, size_t bytes, hipStream_t s, void** out) {
+        if (!arena) return ws_get(ctx, slot, bytes, s, out);
+        const size_t off = (used + 255) & ~size_t(255);
+        if (bytes > cap || off > cap - bytes)
+            return fail(CORR_EINVAL, "the call needs more than the " + std::to_string(cap >> 20) +
+                                         " MiB of fixed scratch (at least " + std::to_string(off + bytes) + " bytes)");
+        *out = arena + off;
+        used = off + bytes;
+        return CORR_OK;
+    }
+};
 
 int kernel_setup(const void* fn, size_t lds, int threads, int* per_cu) {
     struct Key {
@@ -156,12 +202,12 @@ static int64_t overlap_count(const Box& a, const Box& b) {
 static bool stats_acc64(int measure, int M) { return measure == CORR_KSG || M > 256; }
 
 // Standardise the points of `box` into (stats slot, hi slot, lo slot).
-static int standardize_box(corr_ctx* ctx, const corr_field& f, const Box& box, bool acc64, int fmt, int64_t rows_pad,
+static int standardize_box(Ws& w, const corr_field& f, const Box& box, bool acc64, int fmt, int64_t rows_pad,
                            int64_t ld, int stats_slot, int hi_slot, int lo_slot, hipStream_t s, Stats* st_out,
                            void** hi, void** lo) {
     const int64_t n = box.count();
     void* sb = nullptr;
-    int rc = ws_get(ctx, stats_slot, sizeof(float) * 4 * (size_t)n, s, &sb);
+    int rc = w.get(stats_slot, sizeof(float) * 4 * (size_t)n, s, &sb);
     if (rc) return rc;
     Stats st = stats_view((float*)sb, n);
     if (fmt != ZF_RAW) {
@@ -169,11 +215,11 @@ static int standardize_box(corr_ctx* ctx, const corr_field& f, const Box& box, b
         if (rc) return rc;
     }
     size_t es = (fmt == ZF_KSG || fmt == ZF_RAW || fmt == ZF_F32) ? 4 : 2;
-    rc = ws_get(ctx, hi_slot, es * (size_t)(rows_pad * ld), s, hi);
+    rc = w.get(hi_slot, es * (size_t)(rows_pad * ld), s, hi);
     if (rc) return rc;
     *lo = nullptr;
     if (fmt == ZF_F16X2 || fmt == ZF_BF16X2) {
-        rc = ws_get(ctx, lo_slot, es * (size_t)(rows_pad * ld), s, lo);
+        rc = w.get(lo_slot, es * (size_t)(rows_pad * ld), s, lo);
         if (rc) return rc;
     }
     rc = launch_transpose(f, box, st, fmt, *hi, *lo, rows_pad, ld, s);
@@ -183,11 +229,11 @@ static int standardize_box(corr_ctx* ctx, const corr_field& f, const Box& box, b
 }
 
 // Each standardised row sorted ascending (the marginals KSG counts on).
-static int sorted_rows(corr_ctx* ctx, const float* z, int64_t ld, int64_t nrows, int M, int slot, hipStream_t s,
+static int sorted_rows(Ws& w, const float* z, int64_t ld, int64_t nrows, int M, int slot, hipStream_t s,
                        void** out) {
-    int rc = ws_get(ctx, slot, sizeof(float) * (size_t)nrows * ksg_p2(M), s, out);
+    int rc = w.get(slot, sizeof(float) * (size_t)nrows * ksg_p2(M), s, out);
     if (rc) return rc;
-    return launch_sort_rows(z, ld, nrows, M, (float*)*out, ctx->num_cus, s);
+    return launch_sort_rows(z, ld, nrows, M, (float*)*out, w.ctx->num_cus, s);
 }
 
 static int read_keys(corr_ctx* ctx, hipStream_t s, unsigned long long* k0, unsigned long long* k1) {
@@ -256,8 +302,9 @@ static void tune_store(corr_ctx* ctx, const corr_tune_rec& rec) {
 // Exhaustive Pearson region maximum: standardise both regions into the
 // contraction layout, run the fused MFMA contraction, decode the key.
 // cfg < 0 selects the tuned (or default) small-K configuration.
-static int pearson_exhaustive(corr_ctx* ctx, const corr_field& A, const Box& ba, const corr_field& B, const Box& bb,
+static int pearson_exhaustive(Ws& w, const corr_field& A, const Box& ba, const corr_field& B, const Box& bb,
                               bool sf, int prec, int cfg, corr_max* out, hipStream_t s) {
+    corr_ctx* ctx = w.ctx;
     const int64_t na = ba.count(), nb = bb.count();
     const bool acc64 = stats_acc64(CORR_PEARSON, A.M);
     const int fmt = zfmt_for_prec(prec);
@@ -278,15 +325,15 @@ static int pearson_exhaustive(corr_ctx* ctx, const corr_field& A, const Box& ba,
     void *ah, *al, *bh, *bl;
     int rc = launch_fill_u64(ctx->keys, 2, 0ull, s);
     if (rc) return rc;
-    rc = standardize_box(ctx, A, ba, acc64, fmt, na_pad, K, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
+    rc = standardize_box(w, A, ba, acc64, fmt, na_pad, K, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
     if (rc) return rc;
-    rc = standardize_box(ctx, B, bb, acc64, fmt, nb_pad, K, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
+    rc = standardize_box(w, B, bb, acc64, fmt, nb_pad, K, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
     if (rc) return rc;
     const int32_t* self_col = nullptr;
     int64_t n_self = 0;
     if (sf && boxes_overlap(ba, bb)) {
         void* m = nullptr;
-        rc = ws_get(ctx, WS_MISC, sizeof(int32_t) * (size_t)na, s, &m);
+        rc = w.get(WS_MISC, sizeof(int32_t) * (size_t)na, s, &m);
         if (rc) return rc;
         self_col_kernel<<<dim3((unsigned)((na + 255) / 256)), 256, 0, s>>>(ba, bb, (int32_t*)m);
         CORR_LAUNCH_CHECK();
@@ -365,6 +412,11 @@ int corr_create(int device, corr_ctx** out) {
         corr_destroy(c);
         return fail(CORR_EHIP, std::string("corr_create: ") + hipGetErrorString(e));
     }
+    if (scratch_address(device, &c->scratch) != CORR_OK) {
+        const std::string msg = "corr_create: " + g_last_error;
+        corr_destroy(c);
+        return fail(CORR_EHIP, msg);
+    }
     *out = c;
     return CORR_OK;
 }
@@ -425,12 +477,13 @@ int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, con
     int best = -1;
     float best_t = 0.0f;
     std::vector<float> t(reps);
+    Ws w{ctx};
     for (int cfg = 0; cfg < smallk_num_configs(); ++cfg) {
         if (!smallk_config_ok(prec, cfg, smallk_pad_K(A->M))) continue;
         corr_max tmp;
-        rc = pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);  // warm-up
+        rc = pearson_exhaustive(w, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);  // warm-up
         for (int r = 0; r < reps && rc == CORR_OK; ++r) {
-            rc = pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);
+            rc = pearson_exhaustive(w, *A, ba, *B, bb, sf, prec, cfg, &tmp, s);
             if (rc == CORR_OK) rc = corr_kernel_time_ms(ctx, TK_GEMM, &t[r]);
         }
         if (rc) {
@@ -469,6 +522,7 @@ int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     int best = -1;
     float best_t = 0.0f;
     std::vector<float> t(reps);
+    Ws w{ctx};
     static const int cands[] = {1, 2, 4, 8, 16};
     // remove any previous choice so each candidate runs as given
     for (size_t i = 0; i < ctx->tune.size(); ++i)
@@ -575,14 +629,15 @@ int corr_pearson_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, 
     const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
     Box ba = whole_box(*A), bb = whole_box(*B);
     void *ah, *al, *bh, *bl;
-    rc = standardize_box(ctx, *A, ba, acc64, zfmt_for_prec(prec), ba.count(), ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s,
+    Ws w{ctx};
+    rc = standardize_box(w, *A, ba, acc64, zfmt_for_prec(prec), ba.count(), ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s,
                          nullptr, &ah, &al);
     if (rc) return rc;
     if (same_field(*A, *B)) {
         bh = ah;
         bl = al;
     } else {
-        rc = standardize_box(ctx, *B, bb, acc64, zfmt_for_prec(prec), bb.count(), ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s,
+        rc = standardize_box(w, *B, bb, acc64, zfmt_for_prec(prec), bb.count(), ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s,
                              nullptr, &bh, &bl);
         if (rc) return rc;
     }
@@ -613,23 +668,24 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     Box ba = whole_box(*A), bb = whole_box(*B);
     Stats sa{}, sb{};
     void *za, *zb, *unused;
-    rc = standardize_box(ctx, *A, ba, true, fmt, ba.count(), ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
+    Ws w{ctx};
+    rc = standardize_box(w, *A, ba, true, fmt, ba.count(), ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
     if (rc) return rc;
     if (same_field(*A, *B)) {
         zb = za;
         sb = sa;
     } else {
-        rc = standardize_box(ctx, *B, bb, true, fmt, bb.count(), ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb,
+        rc = standardize_box(w, *B, bb, true, fmt, bb.count(), ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb,
                              &unused);
         if (rc) return rc;
     }
     void *sra, *srb;
-    rc = sorted_rows(ctx, (const float*)za, ld, ba.count(), A->M, WS_SORT_A, s, &sra);
+    rc = sorted_rows(w, (const float*)za, ld, ba.count(), A->M, WS_SORT_A, s, &sra);
     if (rc) return rc;
     if (zb == za) {
         srb = sra;
     } else {
-        rc = sorted_rows(ctx, (const float*)zb, ld, bb.count(), A->M, WS_SORT_B, s, &srb);
+        rc = sorted_rows(w, (const float*)zb, ld, bb.count(), A->M, WS_SORT_B, s, &srb);
         if (rc) return rc;
     }
     KsgArgs a{};
@@ -661,9 +717,14 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     return rc;
 }
 
-int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
-                    const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
-                    int64_t n_samples, corr_max* out, corr_stream_t stream) {
+}  // extern "C"
+
+// Region maximum (exhaustive Pearson, or Pearson / KSG over a sample list)
+// with its workspaces taken from `w`.
+static int region_max_impl(Ws& w, const corr_field* A, const corr_region* ra, const corr_field* B,
+                           const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                           int64_t n_samples, corr_max* out, hipStream_t s) {
+    corr_ctx* ctx = w.ctx;
     if (!ctx) return fail(CORR_EINVAL, "null context");
     if (!out) return fail(CORR_EINVAL, "null output");
     int rc = check_field(A, "A");
@@ -683,7 +744,6 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     if (n_samples < 0) return fail(CORR_EINVAL, "n_samples < 0");
     if (sample_pairs == nullptr && n_samples != 0)
         return fail(CORR_EINVAL, "n_samples given without sample_pairs");
-    hipStream_t s = (hipStream_t)stream;
     Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
     const int64_t na = ba.count(), nb = bb.count();
     if (na * nb >= (int64_t(1) << 31)) return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
@@ -699,11 +759,11 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
         const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
         const int fmt = zfmt_for_prec(prec);
         void *ah, *al, *bh, *bl;
-        if (exhaustive) return pearson_exhaustive(ctx, *A, ba, *B, bb, sf, prec, -1, out, s);
+        if (exhaustive) return pearson_exhaustive(w, *A, ba, *B, bb, sf, prec, -1, out, s);
         const int64_t ld = round_up(A->M, 16);
-        rc = standardize_box(ctx, *A, ba, acc64, fmt, na, ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
+        rc = standardize_box(w, *A, ba, acc64, fmt, na, ld, WS_STATS_A, WS_ZH_A, WS_ZL_A, s, nullptr, &ah, &al);
         if (rc) return rc;
-        rc = standardize_box(ctx, *B, bb, acc64, fmt, nb, ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
+        rc = standardize_box(w, *B, bb, acc64, fmt, nb, ld, WS_STATS_B, WS_ZH_B, WS_ZL_B, s, nullptr, &bh, &bl);
         if (rc) return rc;
         timing_begin(ctx, TK_PAIRS, s);
         rc = launch_pearson_pairs(prec, ah, al, bh, bl, ld, sample_pairs, n_samples, nullptr, ba, bb, sf ? 1 : 0,
@@ -721,14 +781,14 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     const int64_t ld = round_up(A->M, 4);
     Stats sa{}, sb{};
     void *za, *zb, *unused;
-    rc = standardize_box(ctx, *A, ba, true, ZF_KSG, na, ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
+    rc = standardize_box(w, *A, ba, true, ZF_KSG, na, ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &sa, &za, &unused);
     if (rc) return rc;
-    rc = standardize_box(ctx, *B, bb, true, ZF_KSG, nb, ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb, &unused);
+    rc = standardize_box(w, *B, bb, true, ZF_KSG, nb, ld, WS_STATS_B, WS_Z_B, WS_ZL_B, s, &sb, &zb, &unused);
     if (rc) return rc;
     void *sra, *srb;
-    rc = sorted_rows(ctx, (const float*)za, ld, na, A->M, WS_SORT_A, s, &sra);
+    rc = sorted_rows(w, (const float*)za, ld, na, A->M, WS_SORT_A, s, &sra);
     if (rc) return rc;
-    rc = sorted_rows(ctx, (const float*)zb, ld, nb, A->M, WS_SORT_B, s, &srb);
+    rc = sorted_rows(w, (const float*)zb, ld, nb, A->M, WS_SORT_B, s, &srb);
     if (rc) return rc;
     KsgArgs a{};
     a.za = (const float*)za;
@@ -760,6 +820,24 @@ int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, c
     decode_key(k0, ba, bb, false, out);
     out->n_evaluated = (int64_t)k1;
     return CORR_OK;
+}
+
+extern "C" {
+
+int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                    const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                    int64_t n_samples, corr_max* out, corr_stream_t stream) {
+    Ws w{ctx};
+    return region_max_impl(w, A, ra, B, rb, measure, prec, k, sample_pairs, n_samples, out, (hipStream_t)stream);
+}
+
+int corr_region_max_noalloc(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
+                            const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                            int64_t n_samples, corr_max* out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (!ctx->scratch) return fail(CORR_ESTATE, "corr_region_max_noalloc: the context has no fixed scratch");
+    Ws w{ctx, (char*)ctx->scratch, CORR_SCRATCH_BYTES};
+    return region_max_impl(w, A, ra, B, rb, measure, prec, k, sample_pairs, n_samples, out, (hipStream_t)stream);
 }
 
 int corr_block_means(corr_ctx* ctx, const corr_field* A, int f, int out_dtype, void* out, int64_t out_stride,

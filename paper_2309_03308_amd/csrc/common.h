@@ -82,6 +82,7 @@ struct corr_ctx {
     size_t ws_size[corr::WS_COUNT] = {};
     unsigned long long* keys = nullptr;     // device scratch for max keys
     unsigned long long* keys_host = nullptr;  // pinned host mirror
+    void* scratch = nullptr;  // device address of this GPU's fixed scratch (no-allocation calls)
     // kernel timing hook: events per kernel class (see corr_set_timing)
     bool timing = false;
     hipEvent_t ev_start[5] = {};
