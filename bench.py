@@ -207,8 +207,81 @@ def _line(args, value, ms, config, **extra):
     return line
 
 
+FP64_VALU_PEAK = 78.6e12  # MI355X FP64 vector, flop/s
+
+
+def bos_flops(schedule, n_init, C):
+    """FP64 flops of one BOS view, counted from the algorithm at each pair's slot count.
+
+    Per pair and batch (n observations, b picks, C candidates): the Matern
+    covariance (25 flops per entry of the lower triangle), the Cholesky factor
+    (n^3 / 3), the two solves for alpha (2 n^2), per candidate its covariance
+    row, mean and solve vector (25 n + n^2 + 2 n), and per believer pick a
+    covariance, an O(rows) update and a variance per candidate (25 + 2 rows + 4).
+    n is the slot count (an upper bound: repeated cells are not evaluated
+    twice). Returns (total, per-iteration list).
+    """
+    per_iter = {}
+    for sched in schedule:
+        n = n_init
+        for t, b in enumerate(sched):
+            f = 25.0 * n * (n + 1) / 2 + n ** 3 / 3.0 + 2.0 * n * n + C * (25.0 * n + n * n + 2.0 * n)
+            f += sum(C * (29.0 + 2.0 * (n + m)) for m in range(b))
+            per_iter[t] = per_iter.get(t, 0.0) + f
+            n += b
+    its = [per_iter[t] for t in sorted(per_iter)]
+    return sum(its), its
+
+
+def context_cpu_baseline(e, pairs, measure, gpu_res, truth, n_sub, cfg_gpu):
+    """The oracle BOS (FP64 NumPy GP, C objective) on a seeded subset of the region pairs."""
+    import oracle
+    from oracle import bos_ref as B
+    cfg = B.BosConfig(n_init=cfg_gpu.n_init, n_total=cfg_gpu.n_total, n_uniform=cfg_gpu.n_uniform,
+                      n_local=cfg_gpu.n_local, kappa=cfg_gpu.kappa, lengthscale=cfg_gpu.lengthscale,
+                      local_sd=cfg_gpu.local_sd, jitter=cfg_gpu.jitter, seed=cfg_gpu.seed)
+    sub = np.random.default_rng(31).choice(len(pairs), n_sub, replace=False)
+    vals, n_eval = [], 0
+    t0 = time.perf_counter()
+    for p in sub:
+        ia, ib = pairs[p]
+        ra, rb = e.regions[ia], e.regions[ib]
+        dims = (ra.dx, ra.dy, ra.dz, rb.dx, rb.dy, rb.dz)
+
+        def obj(c, ra=ra, rb=rb):
+            pa, pb = B.cells_to_points(c, ra, rb, e.nx, e.ny)
+            pp = np.stack([pa, pb], 1).astype(np.int32)
+            if measure == "pearson":
+                return np.abs(oracle.pearson_pairs(e.data, pp))
+            return oracle.ksg_pairs(e.data, pp, 10, want_counts=False)[0]
+        r = B.run_pair(cfg, int(p), dims, obj)
+        vals.append(r["value"])
+        n_eval += r["n_evaluated"]
+    dt = time.perf_counter() - t0
+    vals = np.array(vals)
+    gpu = np.array([gpu_res[p]["value"] for p in sub])
+    out = {"value": n_eval / dt, "unit": "evaluations/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"oracle BOS (FP64 NumPy GP and acquisition, C objective) on {n_sub} seeded region pairs "
+                     f"of the 3828, {n_eval} evaluations in {dt:.1f} s; a whole view extrapolates to "
+                     f"{dt * len(pairs) / n_sub:.0f} s",
+           "cpu_model": cpu_model(),
+           "gpu_vs_oracle_bos_max_abs": float(np.max(np.abs(gpu - vals))),
+           "gpu_vs_oracle_bos_equal_within_1e-5": float(np.mean(np.abs(gpu - vals) <= 1e-5))}
+    if truth is not None:
+        out["oracle_bos_mean_abs_err_vs_exhaustive"] = float(np.mean(np.abs(truth[sub] - vals)))
+        out["gpu_bos_mean_abs_err_vs_exhaustive_same_pairs"] = float(np.mean(np.abs(truth[sub] - gpu)))
+    return out
+
+
 def run_context(args, torch, synth, pc):
-    """Context view: batched BOS (20 + 80 samples per pair, uneven batches) over all 3828 region pairs."""
+    """Context view: batched BOS (20 + 80 samples per pair, uneven batches) over all 3828 region pairs.
+
+    One step is one whole view: bos_create (standardises the 721 MB field and
+    uploads the schedule), every iteration (one persistent BOS kernel per
+    iteration, replayed from a captured HIP graph), and the read-back of the
+    3828 maxima.
+    """
+    print("context: generating the 352x256x20 ensemble", file=sys.stderr, flush=True)
     e = synth.make_cfg3()
     ctx = pc.Context(0)
     f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
@@ -225,6 +298,7 @@ def run_context(args, torch, synth, pc):
         bos.close()
         return res, steps
 
+    print("context: warm-up views", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         view()
     torch.cuda.synchronize()
@@ -234,8 +308,35 @@ def run_context(args, torch, synth, pc):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     n_eval = sum(r["n_evaluated"] for r in res)
-    extra = {"breakdown": {"bos_iterations": iters + 1, "evaluations": n_eval,
-                           "context_view_ms": ms, "region_pairs": len(pairs)}}
+    print(f"context: {ms:.1f} ms per view", file=sys.stderr, flush=True)
+
+    # phases of one more view, each timed with HIP events on the stream the work runs on
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    bos = pc.Bos(ctx, f, regions, pairs, cfg)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    create_ms = ev[0].elapsed_time(ev[1])
+    it_ms = []
+    while True:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        active = bos.bos_sample_step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        it_ms.append(a.elapsed_time(b))
+        if active == 0:
+            break
+    schedule = bos.bos_schedule()
+    bos.close()
+    flops, flops_it = bos_flops(schedule, cfg.n_init, cfg.n_uniform + cfg.n_local)
+    kern_ms = sum(it_ms)
+    breakdown = {"bos_iterations": len(it_ms), "evaluations": n_eval, "context_view_ms": ms,
+                 "region_pairs": len(pairs), "create_ms": create_ms, "iteration_ms": it_ms,
+                 "bos_kernels_ms": kern_ms, "evaluations_per_s": n_eval / (ms / 1e3),
+                 "bos_fp64_gflop_per_view": flops / 1e9}
+    truth = None
     if args.measure == "pearson":
         truth = np.array([ctx.corr_region_max(f, regions[i], regions[j], "pearson", "f16x3")["value"]
                           for i, j in pairs])
@@ -244,16 +345,33 @@ def run_context(args, torch, synth, pc):
         for gr in e.groups:
             rs = set(gr["regions"])
             planted |= np.array([(i in rs and j in rs) for i, j in pairs])
-        extra["bos_error_vs_exhaustive"] = {
+        noise = ~planted
+        breakdown["bos_error_vs_exhaustive_f16x3"] = {
             "mean_abs": float(np.abs(err).mean()), "max_abs": float(np.abs(err).max()),
             "frac_within_0.01": float(np.mean(np.abs(err) <= 0.01)),
             "planted_pairs": int(planted.sum()),
             "planted_mean_abs": float(np.abs(err[planted]).mean()) if planted.any() else None,
+            "planted_frac_within_0.01": float(np.mean(np.abs(err[planted]) <= 0.01)) if planted.any() else None,
+            "noise_pairs": int(noise.sum()),
+            "noise_mean_abs": float(np.abs(err[noise]).mean()),
+            "noise_frac_within_0.01": float(np.mean(np.abs(err[noise]) <= 0.01)),
             "normalized_mean": float((err / truth).mean())}
+    roofline = {"bound": "alu", "achieved": flops / (kern_ms / 1e3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": flops / (kern_ms / 1e3) / FP64_VALU_PEAK, "traffic": None,
+                "kernel": "bos_kernel (all iterations of one view)",
+                "work": "FP64 flops of the GP factorisation, posterior over 512 candidates and Kriging-believer "
+                        "updates per pair and batch, counted at the slot count; iterations timed with HIP events "
+                        "on the stream they run on"}
+    extra = {"breakdown": breakdown, "roofline": roofline}
+    if not args.no_cpu_baseline:
+        print("context: oracle BOS on 100 region pairs", file=sys.stderr, flush=True)
+        extra["cpu_baseline"] = context_cpu_baseline(e, pairs, args.measure, res, truth, 100, cfg)
     line = _line(args, n_eval / (ms / 1e3), ms,
                  {"workload": f"context view: 352x256x20 ensemble, M=100 FP32, 88 regions of 32x32x20, 3828 "
                               f"region pairs, batched BOS ({args.measure}, 20 + 80 samples per pair)",
                   "members": 100, "region_pairs": len(pairs), "measure": args.measure}, **extra)
+    line["unit"] = "evaluated point pairs/s"
+    line["dtype"] = "f64 GP, f32 objective"
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -129,6 +129,12 @@ int bos_results(bos_state* st, corr_max* out, corr_stream_t stream);
 int bos_history(bos_state* st, int32_t pair, int32_t* cells, float* values, int32_t* n_out,
                 corr_stream_t stream);
 
+/* The uneven batch schedule drawn from the seed (Sec. 3.1 batching, the rule
+ * in the header comment): sched_out HOST int32 [n_pairs][16] receives each
+ * pair's batch sizes in order (unused entries 0), n_batches_out HOST int32
+ * [n_pairs] the number of batches. Host-only; no GPU work. */
+int bos_schedule(bos_state* st, int32_t* sched_out, int32_t* n_batches_out);
+
 /* Save / restore the sampling state (observations, schedules, iteration)
  * to / from a file; the restored state continues bit-identically. load
  * requires a state created with the same fields, pairs and config. */

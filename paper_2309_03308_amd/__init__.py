@@ -376,6 +376,14 @@ class Bos:
                                       ctypes.c_void_p(vals.ctypes.data), ctypes.byref(n), _stream_ptr(stream)))
         return cells[: n.value].copy(), vals[: n.value].copy()
 
+    def bos_schedule(self):
+        """Per pair, the batch sizes drawn from the seed: a list of lists."""
+        import numpy as np
+        sched = np.zeros((self.n_pairs, 16), np.int32)
+        nb = np.zeros(self.n_pairs, np.int32)
+        _lib.check(self.L.bos_schedule(self.h, ctypes.c_void_p(sched.ctypes.data), ctypes.c_void_p(nb.ctypes.data)))
+        return [list(sched[p, : nb[p]]) for p in range(self.n_pairs)]
+
     def bos_save(self, path: str, stream=None):
         _lib.check(self.L.bos_save(self.h, path.encode(), _stream_ptr(stream)))
 

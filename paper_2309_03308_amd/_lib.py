@@ -87,6 +87,7 @@ SIGNATURES = {
     "bos_run": (_I, [_P, _P]),
     "bos_results": (_I, [_P, ctypes.POINTER(corr_max), _P]),
     "bos_history": (_I, [_P, _I32, _P, _P, ctypes.POINTER(_I32), _P]),
+    "bos_schedule": (_I, [_P, _P, _P]),
     "bos_save": (_I, [_P, ctypes.c_char_p, _P]),
     "bos_load": (_I, [_P, ctypes.c_char_p, _P]),
     "bos_destroy": (None, [_P]),

@@ -1189,6 +1189,15 @@ int bos_history(bos_state* st, int32_t pair, int32_t* cells, float* values, int3
     return CORR_OK;
 }
 
+int bos_schedule(bos_state* st, int32_t* sched_out, int32_t* n_batches_out) {
+    if (!st || !sched_out || !n_batches_out) return fail(CORR_EINVAL, "bos_schedule: null argument");
+    for (int p = 0; p < st->n_pairs; ++p) {
+        n_batches_out[p] = st->h_nsched[p];
+        for (int i = 0; i < 16; ++i) sched_out[16 * p + i] = st->h_sched[16 * (size_t)p + i];
+    }
+    return CORR_OK;
+}
+
 static const char kBosMagic[8] = {'B', 'O', 'S', 'S', 'T', 'A', 'T', '2'};
 
 int bos_save(bos_state* st, const char* path, corr_stream_t stream) {

@@ -212,3 +212,15 @@ def test_bos_error_paths(env):
     b.bos_run()
     assert b.bos_sample_step() == 0  # done: further steps do nothing
     b.close()
+
+
+def test_bos_schedule_matches_oracle(env):
+    pc = env["pc"]
+    cfg = pc.bos_defaults(seed=7)
+    b = _bos(env, cfg)
+    sched = b.bos_schedule()
+    ocfg = _oracle_cfg(cfg)
+    for p in range(len(env["pairs"])):
+        assert [int(v) for v in sched[p]] == B.schedule(ocfg, p)
+        assert sum(sched[p]) == cfg.n_total - cfg.n_init and all(8 <= v <= 64 and v % 8 == 0 for v in sched[p])
+    b.close()
