@@ -51,6 +51,44 @@ struct Box {
     }
 };
 
+// Division of 0 <= n < 2^31 by a divisor 1 <= d < 2^31 fixed for a launch:
+// a multiply-high and two shifts instead of a full integer division
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, the unsigned case with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1).
+struct FastDiv {
+    uint32_t d = 1, m = 1, s1 = 0, s2 = 0;
+    __host__ __device__ FastDiv() {}
+    __host__ explicit FastDiv(uint32_t dd) {
+        d = dd;
+        uint32_t l = 0;
+        while (l < 32 && (uint64_t(1) << l) < dd) ++l;
+        m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - dd)) / dd + 1);
+        s1 = l == 0 ? 0u : 1u;
+        s2 = l == 0 ? 0u : l - 1;
+    }
+    __host__ __device__ uint32_t div(uint32_t n) const {
+#ifdef __HIP_DEVICE_COMPILE__
+        const uint32_t t = __umulhi(m, n);
+#else
+        const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+#endif
+        return (t + ((n - t) >> s1)) >> s2;
+    }
+};
+
+// Local index of global point p in box b (grid divisors dx = nx, dy = ny),
+// or -1 if outside; the same as Box::local with invariant divisions.
+__host__ __device__ inline int64_t box_local_fast(const Box& b, const FastDiv& dx, const FastDiv& dy, int32_t p) {
+    const uint32_t r = dx.div((uint32_t)p);
+    const int32_t x = p - (int32_t)(r * dx.d) - b.x0;
+    const uint32_t zq = dy.div(r);
+    const int32_t y = (int32_t)(r - zq * dy.d) - b.y0;
+    const int32_t z = (int32_t)zq - b.z0;
+    if (x < 0 || y < 0 || z < 0 || x >= b.dx || y >= b.dy || z >= b.dz) return -1;
+    return x + (int64_t)b.dx * (y + (int64_t)b.dy * z);
+}
+
 // ---- workspace --------------------------------------------------------------
 enum WsSlot {
     WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
@@ -150,6 +188,8 @@ struct KsgArgs {
     int pw;                // workgroups per CU cap of the resident grid (<= 0: the occupancy limit)
     unsigned long long* work;  // device word the waves take pair chunks from (zeroed by launch_ksg)
     int whole_a, whole_b;  // box covers the whole grid: local index = global index
+    FastDiv ax, ay, bx, by;  // grid divisors nx, ny of the boxes' fields (set by launch_ksg)
+    FastDiv nbd;             // number of points of box b (implicit all pairs; set by launch_ksg)
 };
 int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s);
 int ksg_p2(int M);

@@ -190,13 +190,13 @@ __global__ __launch_bounds__(256) void ksg_kernel(KsgArgs a, int64_t n_total, Ks
             bool same = false;
             if (a.pairs) {
                 const int32_t ga = a.pairs[2 * t], gb = a.pairs[2 * t + 1];
-                la = a.whole_a ? ga : (int)a.ba.local(ga);
-                lb = a.whole_b ? gb : (int)a.bb.local(gb);
+                la = a.whole_a ? ga : (ga < 0 ? -1 : (int)box_local_fast(a.ba, a.ax, a.ay, ga));
+                lb = a.whole_b ? gb : (gb < 0 ? -1 : (int)box_local_fast(a.bb, a.bx, a.by, gb));
                 same = ga == gb;
             } else {
-                const int32_t tt = (int32_t)t, nb32 = (int32_t)nb;
-                la = tt / nb32;
-                lb = tt - la * nb32;
+                const int32_t tt = (int32_t)t;
+                la = (int32_t)a.nbd.div((uint32_t)tt);
+                lb = tt - la * (int32_t)a.nbd.d;
                 same = a.ba.global(la) == a.bb.global(lb);
             }
             // state: 0 = nothing to evaluate, 1 = evaluate, 2 = constant point (MI 0)
@@ -553,9 +553,16 @@ static int launch_p2(const KsgArgs& a, int64_t n_total, const KsgLayout& L, int 
     }
 }
 
-int launch_ksg(const KsgArgs& a, int num_cus, hipStream_t s) {
+int launch_ksg(const KsgArgs& a_in, int num_cus, hipStream_t s) {
+    KsgArgs a = a_in;
     int64_t n_total = a.pairs ? a.n : a.ba.count() * a.bb.count();
     if (n_total == 0) return CORR_OK;
+    if (!a.pairs && n_total >= (int64_t(1) << 31)) return fail(CORR_EUNSUPPORTED, "KSG: 2^31 or more implicit pairs");
+    a.ax = FastDiv((uint32_t)a.ba.nx);
+    a.ay = FastDiv((uint32_t)a.ba.ny);
+    a.bx = FastDiv((uint32_t)a.bb.nx);
+    a.by = FastDiv((uint32_t)a.bb.ny);
+    a.nbd = FastDiv((uint32_t)std::max<int64_t>(1, a.bb.count()));
     const KsgLayout L = ksg_layout(a.M);
     const size_t lds = ksg_lds_bytes(a.M, a.pw);
     if (lds > 160 * 1024) return fail(CORR_EUNSUPPORTED, "KSG: member count too large for the LDS layout");
