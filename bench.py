@@ -12,9 +12,15 @@ correlated blobs), regions A = x in [0,32) and B = x in [48,80) of 32x32x20 =
     with its region maximum fused (corr_region_max over the sample list).
 
 value = (Pearson pairs + KSG pairs) per second of step time, inputs resident
-in HBM. The JSON line also carries the per-measure rates, a roofline entry for
-the dominant kernel (timed live with HIP events on the stream it runs on) and
-the CPU oracle's rate on a bounded sample of the same workload.
+in HBM: the throughput of one whole step. The JSON line also carries a
+roofline entry for the step's dominant kernel (KSG; timed live with HIP
+events on the stream it runs on), the CPU oracle's rate on a bounded sample
+of the same workload, and `per_measure`: point pairs/s of each measure at
+M = 100 (this field) and M = 1000 (the 128x128x32 FP16 large-ensemble field:
+4e6 random pairs for Pearson and KSG on fields prepared once, and the
+exhaustive contraction of two 16^3 regions), each leg with its own roofline
+(MFMA for the contractions, HBM for the pair-list gather, VALU for KSG),
+oracle baseline and error against the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -132,6 +138,7 @@ def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
     mi_gpu, cnt_gpu = ctx.corr_ksg_mi_pairs(f, torch.from_numpy(ks).cuda(), k=10, counts=True)
     ref_max = oracle.pearson_region_max_matmul(e.data, ia, ib, block=2048)
     err = {
+        "_ref_max": float(ref_max["value"]),
         "pearson_f16_pairs_max_abs": float(np.max(np.abs(r_gpu - r_ref))),
         "pearson_region_max_abs": float(abs(ctx_results["pearson"]["value"] - ref_max["value"])),
         "ksg_mi_max_abs": float(np.max(np.abs(mi_gpu.cpu().numpy() - mi_ref))),
@@ -146,6 +153,8 @@ def cpu_baseline(e, pairs_np, ctx_results, f, ctx, torch, pc):
                    f"{n_k} of the 1e6 sampled pairs ({t_k * 1e6:.1f} us/pair), extrapolated to one step "
                    f"(4.19e8 Pearson + 1e6 KSG pairs)"),
         "cpu_model": cpu_model(),
+        "pearson_value": 1.0 / t_p,
+        "ksg_value": 1.0 / t_k,
         "single_core_value": (N_PEARSON + N_KSG) / t_step1,
         "single_core_sample": f"1e6 Pearson pairs ({t_p1 * 1e9:.1f} ns/pair), 1e4 KSG pairs ({t_k1 * 1e6:.1f} us/pair)",
     }, err
@@ -167,6 +176,8 @@ def main():
                          "sampled maxima over those pairs and on 6-D Gaussian test objectives")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="focus: leave out the M=1000 legs (large-ensemble field) of the per-measure breakdown")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (scale reference for HBM byte counters)")
     args = ap.parse_args()
@@ -654,6 +665,130 @@ def run_samplers(args, torch, synth, pc):
     print(json.dumps(line), flush=True)
 
 
+def _timed(torch, fn, reps, warmup, ctx=None, cls=None):
+    """Mean wall time per call (s) and, with a timing class, mean kernel time (ms) from HIP events."""
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    ks = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+        if cls:
+            ks.append(ctx.kernel_time_ms(cls))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, (float(np.mean(ks)) if ks else None)
+
+
+def large_legs(args, torch, synth, pc):
+    """The M = 1000 half of the metric on the 128x128x32 large-ensemble field (FP16 storage).
+
+    Pearson and KSG on 4e6 random point pairs (fields prepared once: the
+    statistics, rows and sorted rows are computed outside the timed calls and
+    their time is reported beside), and the exhaustive contraction of two
+    16^3 regions. Each leg carries its own roofline and oracle baseline.
+    """
+    import oracle
+    print("bench: generating the 128x128x32 M=1000 ensemble", file=sys.stderr, flush=True)
+    e = synth.make_cfg4()
+    P, Mb = e.nx * e.ny * e.nz, e.data.shape[0]
+    ctx = pc.Context(0)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    n = 4_000_000
+    pairs_np = synth.random_pairs(104, n, P)
+    pairs = torch.from_numpy(pairs_np).cuda()
+    out = torch.empty(n, device="cuda")
+    ra, rb = [pc.region(*r.as_tuple()) for r in e.regions]
+    ctx.set_timing(True)
+    legs = {}
+    reps = max(3, args.steps // 2)
+
+    # Pearson pair list, FP16 rows (provably within 9.8e-4 of the FP64 value)
+    t0 = time.perf_counter()
+    pp = ctx.corr_prepare(f, "pearson", "f16")
+    torch.cuda.synchronize()
+    prep_p = (time.perf_counter() - t0) * 1e3
+    t_call, k_ms = _timed(torch, lambda: ctx.corr_pearson_pairs_prepared(pp, pairs, out=out), reps, args.warmup,
+                          ctx, "pairs")
+    t_unprep, _ = _timed(torch, lambda: ctx.corr_pearson_pairs(f, pairs, "f16", out=out), 3, 1)
+    r_gpu = ctx.corr_pearson_pairs_prepared(pp, pairs, out=out).cpu().numpy()
+    pp.close()
+    byt = n * 2.0 * Mb * 2.0  # two FP16 member rows per pair
+    legs["pearson_pairs_m1000"] = {
+        "value": n / (k_ms / 1e3), "unit": "point pairs/s", "kernel_ms": k_ms, "call_ms": t_call * 1e3,
+        "prepare_ms": prep_p, "per_call_standardising_pairs_per_s": n / t_unprep, "precision": "f16",
+        "pairs": n, "roofline": {"bound": "hbm", "achieved": byt / (k_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
+                                 "unit": "GB/s", "frac": byt / (k_ms / 1e3) / HBM_PEAK, "traffic": None,
+                                 "kernel": "pearson pair-list gather (FP16 rows)",
+                                 "work": "2 x 1000 x 2 B of member values per pair"}}
+
+    # KSG pair list, k = 10
+    t0 = time.perf_counter()
+    pk = ctx.corr_prepare(f, "ksg")
+    torch.cuda.synchronize()
+    prep_k = (time.perf_counter() - t0) * 1e3
+    t_call, k_ms = _timed(torch, lambda: ctx.corr_ksg_mi_pairs_prepared(pk, pairs, k=10, out=out), 2, 1, ctx, "ksg")
+    mi_gpu = ctx.corr_ksg_mi_pairs_prepared(pk, pairs, k=10, out=out).cpu().numpy()
+    ops = n * Mb * (Mb - 1) * 3.0
+    legs["ksg_m1000"] = {
+        "value": n / (k_ms / 1e3), "unit": "point pairs/s", "kernel_ms": k_ms, "call_ms": t_call * 1e3,
+        "prepare_ms": prep_k, "k": 10, "pairs": n,
+        "roofline": {"bound": "alu", "achieved": ops / (k_ms / 1e3) / 1e12, "peak": VALU_LANE_OPS_PER_S / 1e12,
+                     "unit": "Tops/s", "frac": ops / (k_ms / 1e3) / VALU_LANE_OPS_PER_S, "traffic": None,
+                     "kernel": "ksg_kernel<10, 0, true>",
+                     "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair"}}
+
+    # exhaustive contraction of the two 16^3 focus regions
+    nf = 4096 * 4096
+    _, g_ms = _timed(torch, lambda: ctx.corr_region_max(f, ra, rb, "pearson", "f16"), reps, args.warmup, ctx, "gemm")
+    g_call, _ = _timed(torch, lambda: ctx.corr_region_max(f, ra, rb, "pearson", "f16"), reps, 1)
+    focus = ctx.corr_region_max(f, ra, rb, "pearson", "f16")
+    fl = 2.0 * Mb * nf
+    legs["pearson_allpairs_m1000"] = {
+        "value": nf / (g_ms / 1e3), "unit": "point pairs/s", "kernel_ms": g_ms, "call_ms": g_call * 1e3,
+        "precision": "f16", "pairs": nf,
+        "roofline": {"bound": "mfma", "achieved": fl / (g_ms / 1e3) / 1e12, "peak": MFMA_F16_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fl / (g_ms / 1e3) / MFMA_F16_PEAK, "traffic": None,
+                     "kernel": "gemm_max_kernel (K = 1008)", "work": "2 M flops per point pair"}}
+
+    if not args.no_cpu_baseline:
+        print("bench: oracle at M = 1000", file=sys.stderr, flush=True)
+        rng = np.random.default_rng(78)
+        sp = rng.choice(n, 200_000, replace=False)
+        t0 = time.perf_counter()
+        r_ref = oracle.pearson_pairs(e.data, pairs_np[sp])
+        tp = (time.perf_counter() - t0) / sp.size
+        sk = sp[:4000]
+        t0 = time.perf_counter()
+        mi_ref, cnt_ref = oracle.ksg_pairs(e.data, pairs_np[sk], 10)
+        tk = (time.perf_counter() - t0) / sk.size
+        _, cnt_gpu = ctx.corr_ksg_mi_pairs(f, torch.from_numpy(np.ascontiguousarray(pairs_np[sk[:200]])).cuda(),
+                                           k=10, counts=True)
+        ia = e.regions[0].global_indices(e.nx, e.ny)
+        ib = e.regions[1].global_indices(e.nx, e.ny)
+        t0 = time.perf_counter()
+        fref = oracle.pearson_region_max_matmul(e.data, ia, ib, block=2048)
+        tf = time.perf_counter() - t0
+        cores = oracle.num_threads()
+        legs["pearson_pairs_m1000"]["max_err_vs_fp64_oracle"] = float(np.max(np.abs(r_gpu[sp] - r_ref)))
+        legs["pearson_pairs_m1000"]["cpu_baseline"] = {
+            "value": 1.0 / tp, "unit": "point pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 two-pass Pearson on 200000 of the 4e6 pairs ({tp * 1e9:.0f} ns/pair)"}
+        legs["ksg_m1000"]["max_err_vs_fp64_oracle"] = float(np.max(np.abs(mi_gpu[sk] - mi_ref)))
+        legs["ksg_m1000"]["count_mismatches_200_pairs"] = int((cnt_gpu.cpu().numpy() != cnt_ref[:200]).sum())
+        legs["ksg_m1000"]["cpu_baseline"] = {
+            "value": 1.0 / tk, "unit": "point pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"brute-force KSG on 4000 of the 4e6 pairs ({tk * 1e3:.2f} ms/pair)"}
+        legs["pearson_allpairs_m1000"]["max_err_vs_fp64_oracle"] = float(abs(focus["value"] - fref["value"]))
+        legs["pearson_allpairs_m1000"]["cpu_baseline"] = {
+            "value": nf / tf, "unit": "point pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 row-block matmul over all 4096 x 4096 focus pairs ({tf:.2f} s)"}
+    ctx.close()
+    del f, pairs, out
+    torch.cuda.empty_cache()
+    return legs
+
+
 def run_focus(args, torch, synth, pc):
     e = synth.make_cfg2()
     pairs_np = synth.region_pairs_uniform(102, N_KSG, e.regions[0], e.regions[1], e.nx, e.ny)
@@ -736,12 +871,43 @@ def run_focus(args, torch, synth, pc):
                      "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair, 1e6 pairs per launch",
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"},
     }
+    # the metric per measure and ensemble size; each leg with its own roofline
+    fl = 2.0 * M * N_PEARSON
+    per = {"pearson_allpairs_m100": {
+        "value": N_PEARSON / (gemm_ms / 1e3), "unit": "point pairs/s", "kernel_ms": gemm_ms, "precision": args.prec,
+        "pairs": N_PEARSON,
+        "roofline": {"bound": "mfma", "achieved": fl / (gemm_ms / 1e3) / 1e12, "peak": MFMA_F16_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": fl / (gemm_ms / 1e3) / MFMA_F16_PEAK, "traffic": None,
+                     "kernel": "gemm_smallk_kernel (K = 112)", "work": "2 M flops per point pair"}}}
+    _, g3_ms = _timed(torch, lambda: ctx.corr_region_max(f, ra, rb, "pearson", "f16x3"), 10, 2, ctx, "gemm")
+    res3 = ctx.corr_region_max(f, ra, rb, "pearson", "f16x3")
+    per["pearson_allpairs_m100_f16x3"] = {
+        "value": N_PEARSON / (g3_ms / 1e3), "unit": "point pairs/s", "kernel_ms": g3_ms, "precision": "f16x3",
+        "pairs": N_PEARSON, "note": "three FP16 MFMA passes (hi.hi, hi.lo, lo.hi): the FP32-accuracy form",
+        "roofline": {"bound": "mfma", "achieved": 3 * fl / (g3_ms / 1e3) / 1e12, "peak": MFMA_F16_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": 3 * fl / (g3_ms / 1e3) / MFMA_F16_PEAK, "traffic": None,
+                     "kernel": "gemm_smallk_kernel, split mode", "work": "3 x 2 M flops per point pair"}}
+    per["ksg_m100"] = {"value": N_KSG / (ksg_ms / 1e3), "unit": "point pairs/s", "kernel_ms": ksg_ms, "k": 10,
+                       "pairs": N_KSG, "roofline": line["roofline"]}
     if not args.no_cpu_baseline:
         cb, err = cpu_baseline(e, pairs_np, res, f, ctx, torch, pc)
         line["cpu_baseline"] = cb
+        err["pearson_f16x3_region_max_abs"] = float(abs(res3["value"] - err.pop("_ref_max")))
         line["max_err_vs_fp64_oracle"] = err
-    print(json.dumps(line), flush=True)
+        base = {"cores": cb["cores"], "kind": "oracle", "unit": "point pairs/s"}
+        per["pearson_allpairs_m100"]["cpu_baseline"] = dict(base, value=cb["pearson_value"],
+                                                            sample="FP64 Pearson on 4e7 uniform A x B pairs")
+        per["pearson_allpairs_m100"]["max_err_vs_fp64_oracle"] = err["pearson_region_max_abs"]
+        per["pearson_allpairs_m100_f16x3"]["max_err_vs_fp64_oracle"] = err["pearson_f16x3_region_max_abs"]
+        per["ksg_m100"]["cpu_baseline"] = dict(base, value=cb["ksg_value"],
+                                               sample="brute-force KSG on 4e5 of the 1e6 sampled pairs")
+        per["ksg_m100"]["max_err_vs_fp64_oracle"] = err["ksg_mi_max_abs"]
+        per["ksg_m100"]["count_mismatches"] = err["ksg_count_mismatches"]
     ctx.close()
+    if not args.no_large:
+        per.update(large_legs(args, torch, synth, pc))
+    line["per_measure"] = per
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

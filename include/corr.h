@@ -164,6 +164,43 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
                       corr_stream_t stream);
 
 /*
+ * A field standardised once for many pair-list calls (Sec. 3.2: Pearson
+ * needs only each point's mean and variance, KSG its z-scored samples and,
+ * here, their sorted marginals). corr_pearson_pairs and corr_ksg_mi_pairs
+ * standardise the whole field on every call; a prepared field holds that
+ * work, so repeated calls only gather the rows their pairs name.
+ *  measure CORR_PEARSON: rows in the format of `prec` (as corr_pearson_pairs
+ *    with that prec); CORR_KSG: z-scored FP32 rows, the sorted rows and the
+ *    per-point statistics (as corr_ksg_mi_pairs without CORR_KSG_RAW).
+ * The handle owns its device buffers (about nx*ny*nz*M*(2 or 4) bytes for
+ * Pearson, 2x that plus the sorted rows for KSG) and keeps no reference to
+ * A's data: after A changes, prepare again. It is enqueued on `stream`; use
+ * it on that stream or after synchronising it.
+ */
+typedef struct corr_prepared corr_prepared;
+int corr_prepare(corr_ctx* ctx, const corr_field* A, int measure, int prec, corr_prepared** out,
+                 corr_stream_t stream);
+/* Frees the handle's buffers after synchronising the device. NULL is ignored. */
+void corr_prepared_destroy(corr_prepared* p);
+
+/*
+ * corr_pearson_pairs on prepared fields: A and B (may be the same handle)
+ * prepared for CORR_PEARSON with the same member count and precision; the
+ * results equal corr_pearson_pairs with that precision bit for bit.
+ */
+int corr_pearson_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B,
+                                const int32_t* pairs, int64_t n, float* r_out, corr_stream_t stream);
+
+/*
+ * corr_ksg_mi_pairs on prepared fields (flags 0): A and B (may be the same
+ * handle) prepared for CORR_KSG with the same member count; mi and counts
+ * equal corr_ksg_mi_pairs's bit for bit.
+ */
+int corr_ksg_mi_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B,
+                               const int32_t* pairs, int64_t n, int32_t k, float* mi_out,
+                               int32_t* counts_out, corr_stream_t stream);
+
+/*
  * Region-pair maximum (Sec. 3: the brick-pair indicator is the maximum of
  * the point-to-point correlations between the two bricks).
  *  measure CORR_PEARSON: objective |r|; CORR_KSG: objective MI.

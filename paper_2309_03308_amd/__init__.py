@@ -154,6 +154,34 @@ class Context:
                                             _stream_ptr(stream)))
         return (mi, cnt) if counts else mi
 
+    def corr_prepare(self, A: Field, measure="pearson", prec="f16", stream=None) -> "Prepared":
+        """Standardise A once for many pair-list calls (include/corr.h corr_prepare)."""
+        h = ctypes.c_void_p()
+        _lib.check(self.L.corr_prepare(self.h, ctypes.byref(A.c), MEASURE[measure], PREC[prec], ctypes.byref(h),
+                                       _stream_ptr(stream)))
+        return Prepared(self, h, A, measure, prec)
+
+    def corr_pearson_pairs_prepared(self, A: "Prepared", pairs, B: "Prepared" = None, out=None, stream=None):
+        torch = _torch()
+        B = A if B is None else B
+        pp, n = _pairs_arg(pairs)
+        r = out if out is not None else torch.empty(n, dtype=torch.float32, device=pairs.device)
+        _lib.check(self.L.corr_pearson_pairs_prepared(self.h, A.h, B.h, pp, n, ctypes.c_void_p(r.data_ptr()),
+                                                      _stream_ptr(stream)))
+        return r
+
+    def corr_ksg_mi_pairs_prepared(self, A: "Prepared", pairs, k=10, B: "Prepared" = None, counts=False, out=None,
+                                   stream=None):
+        torch = _torch()
+        B = A if B is None else B
+        pp, n = _pairs_arg(pairs)
+        mi = out if out is not None else torch.empty(n, dtype=torch.float32, device=pairs.device)
+        cnt = torch.empty((n, A.field.M, 2), dtype=torch.int32, device=pairs.device) if counts else None
+        _lib.check(self.L.corr_ksg_mi_pairs_prepared(self.h, A.h, B.h, pp, n, int(k), ctypes.c_void_p(mi.data_ptr()),
+                                                     ctypes.c_void_p(cnt.data_ptr()) if counts else None,
+                                                     _stream_ptr(stream)))
+        return (mi, cnt) if counts else mi
+
     def corr_region_max(self, A: Field, ra: corr_region, rb: corr_region, measure="pearson", prec="f16", k=10,
                         B: Field = None, samples=None, stream=None) -> dict:
         return self._region_max(self.L.corr_region_max, A, ra, rb, measure, prec, k, B, samples, stream)
@@ -308,6 +336,24 @@ def bos_defaults(**overrides) -> bos_config:
             v = MEASURE[v]
         setattr(c, k, v)
     return c
+
+
+class Prepared:
+    """A field standardised once (include/corr.h corr_prepare); owns its device buffers."""
+
+    def __init__(self, ctx, h, field, measure, prec):
+        self.ctx, self.h, self.field, self.measure, self.prec = ctx, h, field, measure, prec
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.L.corr_prepared_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Bos:

@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 namespace corr {
 
@@ -79,7 +80,19 @@ struct Ws {
     char* arena = nullptr;
     size_t cap = 0;
     size_t used = 0;
+    std::vector<void*>* owned = nullptr;  // set: every buffer is a new allocation recorded here
     int get(int slot, size_t bytes, hipStream_t s, void** out) {
+        if (owned) {
+            void* p = nullptr;
+            hipError_t e = hipMalloc(&p, bytes ? bytes : 256);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CORR_ENOMEM, "allocation of " + std::to_string(bytes) + " bytes failed");
+            }
+            owned->push_back(p);
+            *out = p;
+            return CORR_OK;
+        }
         if (!arena) return ws_get(ctx, slot, bytes, s, out);
         const size_t off = (used + 255) & ~size_t(255);
         if (bytes > cap || off > cap - bytes)
@@ -713,6 +726,136 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     a.same_field = 0;
     timing_begin(ctx, TK_KSG, s);
     rc = launch_ksg(a, ctx->num_cus, s);
+    timing_end(ctx, TK_KSG, s);
+    return rc;
+}
+
+}  // extern "C"
+
+// A whole field standardised once (corr_prepare).
+struct corr_prepared {
+    int device = 0;
+    int measure = 0, prec = 0, M = 0;
+    int nx = 0, ny = 0, nz = 0;
+    int64_t ld = 0;
+    Stats st{};
+    void* hi = nullptr;
+    void* lo = nullptr;
+    void* sorted = nullptr;
+    std::vector<void*> bufs;
+};
+
+extern "C" {
+
+void corr_prepared_destroy(corr_prepared* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    for (void* b : p->bufs) (void)hipFree(b);
+    delete p;
+}
+
+int corr_prepare(corr_ctx* ctx, const corr_field* A, int measure, int prec, corr_prepared** out,
+                 corr_stream_t stream) {
+    if (!out) return fail(CORR_EINVAL, "corr_prepare: null out");
+    *out = nullptr;
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    int rc = check_field(A, "A");
+    if (rc) return rc;
+    if (measure != CORR_PEARSON && measure != CORR_KSG) return fail(CORR_EINVAL, "unknown measure");
+    if (measure == CORR_PEARSON && (prec < CORR_PREC_F32 || prec > CORR_PREC_BF16X3))
+        return fail(CORR_EUNSUPPORTED, "unknown precision");
+    if (measure == CORR_KSG && A->M > 2048) return fail(CORR_EUNSUPPORTED, "M > 2048");
+    hipStream_t s = (hipStream_t)stream;
+    corr_prepared* p = new (std::nothrow) corr_prepared();
+    if (!p) return fail(CORR_ENOMEM, "corr_prepare: host allocation failed");
+    p->device = ctx->device;
+    p->measure = measure;
+    p->prec = measure == CORR_PEARSON ? prec : 0;
+    p->M = A->M;
+    p->nx = A->nx;
+    p->ny = A->ny;
+    p->nz = A->nz;
+    Ws w{ctx};
+    w.owned = &p->bufs;
+    const Box box = whole_box(*A);
+    if (measure == CORR_PEARSON) {
+        p->ld = round_up(A->M, 16);
+        rc = standardize_box(w, *A, box, stats_acc64(CORR_PEARSON, A->M), zfmt_for_prec(prec), box.count(), p->ld,
+                             WS_STATS_A, WS_ZH_A, WS_ZL_A, s, &p->st, &p->hi, &p->lo);
+    } else {
+        p->ld = round_up(A->M, 4);
+        rc = standardize_box(w, *A, box, true, ZF_KSG, box.count(), p->ld, WS_STATS_A, WS_Z_A, WS_ZL_A, s, &p->st,
+                             &p->hi, &p->lo);
+        if (!rc) rc = sorted_rows(w, (const float*)p->hi, p->ld, box.count(), A->M, WS_SORT_A, s, &p->sorted);
+    }
+    if (rc) {
+        corr_prepared_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return CORR_OK;
+}
+
+static Box prepared_box(const corr_prepared* p) { return Box{0, 0, 0, p->nx, p->ny, p->nz, p->nx, p->ny}; }
+
+int corr_pearson_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B,
+                                const int32_t* pairs, int64_t n, float* r_out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (!A || !B) return fail(CORR_EINVAL, "null prepared field");
+    if (A->measure != CORR_PEARSON || B->measure != CORR_PEARSON)
+        return fail(CORR_EINVAL, "fields not prepared for Pearson");
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if (A->prec != B->prec) return fail(CORR_EINVAL, "fields prepared with different precisions");
+    if (n < 0) return fail(CORR_EINVAL, "n < 0");
+    if (n == 0) return CORR_OK;
+    if (!pairs || !r_out) return fail(CORR_EINVAL, "null pairs or output");
+    hipStream_t s = (hipStream_t)stream;
+    timing_begin(ctx, TK_PAIRS, s);
+    int rc = launch_pearson_pairs(A->prec, A->hi, A->lo, B->hi, B->lo, A->ld, pairs, n, r_out, prepared_box(A),
+                                  prepared_box(B), 0, nullptr, s);
+    timing_end(ctx, TK_PAIRS, s);
+    return rc;
+}
+
+int corr_ksg_mi_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B,
+                               const int32_t* pairs, int64_t n, int32_t k, float* mi_out, int32_t* counts_out,
+                               corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (!A || !B) return fail(CORR_EINVAL, "null prepared field");
+    if (A->measure != CORR_KSG || B->measure != CORR_KSG) return fail(CORR_EINVAL, "fields not prepared for KSG");
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    if (n < 0) return fail(CORR_EINVAL, "n < 0");
+    if (k < 1 || k > A->M - 1) return fail(CORR_EINVAL, "k must be in [1, M-1]");
+    if (k > 31) return fail(CORR_EUNSUPPORTED, "k > 31");
+    if (n == 0) return CORR_OK;
+    if (!pairs || (!mi_out && !counts_out)) return fail(CORR_EINVAL, "null pairs or outputs");
+    hipStream_t s = (hipStream_t)stream;
+    KsgArgs a{};
+    a.za = (const float*)A->hi;
+    a.zb = (const float*)B->hi;
+    a.sa = (const float*)A->sorted;
+    a.sb = (const float*)B->sorted;
+    a.pw = tuned_ksg_pw(ctx, A->M, k);
+    a.ld = A->ld;
+    a.inv_a = A->st.inv32;
+    a.inv_b = B->st.inv32;
+    a.pairs = pairs;
+    a.n = n;
+    a.M = A->M;
+    a.k = k;
+    a.psi = ctx->psi;
+    a.mi_out = mi_out;
+    a.counts_out = counts_out;
+    a.key = nullptr;
+    a.work = ctx->keys + 8;
+    a.ba = prepared_box(A);
+    a.bb = prepared_box(B);
+    a.whole_a = 1;
+    a.whole_b = 1;
+    a.same_field = 0;
+    timing_begin(ctx, TK_KSG, s);
+    int rc = launch_ksg(a, ctx->num_cus, s);
     timing_end(ctx, TK_KSG, s);
     return rc;
 }
