@@ -48,6 +48,9 @@ HBM_PEAK = 8.0e12
 KSG_SOURCE = os.path.join(ROOT, "paper_2309_03308_amd", "csrc", "ksg.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ksg_focus_1e6_pmc.txt")
 AGG_SOURCE = os.path.join(ROOT, "paper_2309_03308_amd", "csrc", "aggregate.hip")
+PAIRS_SOURCE = os.path.join(ROOT, "paper_2309_03308_amd", "csrc", "pairs.hip")
+PAIRS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pearson_pairs_gather_m1000_pmc.txt")
+KSG1000_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ksg_m1000_4e6_pmc.txt")
 AGG_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "block_means_f2_180x640x704x64_pmc.txt")
 
 
@@ -718,7 +721,8 @@ def large_legs(args, torch, synth, pc):
         "value": n / (k_ms / 1e3), "unit": "point pairs/s", "kernel_ms": k_ms, "call_ms": t_call * 1e3,
         "prepare_ms": prep_p, "per_call_standardising_pairs_per_s": n / t_unprep, "precision": "f16",
         "pairs": n, "roofline": {"bound": "hbm", "achieved": byt / (k_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
-                                 "unit": "GB/s", "frac": byt / (k_ms / 1e3) / HBM_PEAK, "traffic": None,
+                                 "unit": "GB/s", "frac": byt / (k_ms / 1e3) / HBM_PEAK,
+                                 "traffic": measured_traffic(PAIRS_TRAFFIC_FILE, PAIRS_SOURCE, "pairs_source_sha256"),
                                  "kernel": "pearson pair-list gather (FP16 rows)",
                                  "work": "2 x 1000 x 2 B of member values per pair"}}
 
@@ -734,8 +738,8 @@ def large_legs(args, torch, synth, pc):
         "value": n / (k_ms / 1e3), "unit": "point pairs/s", "kernel_ms": k_ms, "call_ms": t_call * 1e3,
         "prepare_ms": prep_k, "k": 10, "pairs": n,
         "roofline": {"bound": "alu", "achieved": ops / (k_ms / 1e3) / 1e12, "peak": VALU_LANE_OPS_PER_S / 1e12,
-                     "unit": "Tops/s", "frac": ops / (k_ms / 1e3) / VALU_LANE_OPS_PER_S, "traffic": None,
-                     "kernel": "ksg_kernel<10, 0, true>",
+                     "unit": "Tops/s", "frac": ops / (k_ms / 1e3) / VALU_LANE_OPS_PER_S,
+                     "traffic": measured_traffic(KSG1000_TRAFFIC_FILE), "kernel": "ksg_kernel<10, 0, true>",
                      "work": "3 VALU lane-ops per Chebyshev distance, M(M-1) distances per pair"}}
 
     # exhaustive contraction of the two 16^3 focus regions
