@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from argmax_checks import check_pearson_argmax
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -55,9 +56,7 @@ def _check(env, data, dims, ra, rb, prec, same=True):
     _say(f"  M={data.shape[0]} {prec} {ra}x{rb}: gpu {got['value']:.6f} oracle {ref['value']:.6f}")
     assert abs(got["value"] - ref["value"]) <= TOL[prec]
     assert got["n_evaluated"] == ref["n_evaluated"]
-    if ref["value"] - ref["second"] > 2 * TOL[prec]:
-        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
-        assert abs(got["signed_value"] - ref["signed_value"]) <= TOL[prec]
+    check_pearson_argmax(got, ref, data, ia, ib, TOL[prec])
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16", "bf16", "f16x3", "bf16x3"])

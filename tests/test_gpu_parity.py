@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from argmax_checks import check_ksg_argmax, check_pearson_argmax
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -184,9 +185,7 @@ def test_region_max_pearson_cfg1(ctx, pc, torch, cfg1, prec):
     _say(f"  region max {prec}: gpu {got['value']:.7f} oracle {ref['value']:.7f}")
     assert abs(got["value"] - ref["value"]) <= TOL[prec]
     assert got["n_evaluated"] == ia.size * ib.size
-    if ref["value"] - ref["second"] > 2 * TOL[prec]:
-        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
-        assert np.sign(got["signed_value"]) == np.sign(ref["signed_value"])
+    check_pearson_argmax(got, ref, cfg1.data, ia, ib, TOL[prec])
 
 
 def test_region_max_ksg_cfg1_exhaustive(ctx, pc, torch, cfg1):
@@ -201,8 +200,7 @@ def test_region_max_ksg_cfg1_exhaustive(ctx, pc, torch, cfg1):
     assert abs(got["value"] - ref["value"]) <= MI_TOL
     assert got["n_evaluated"] == ia.size * ib.size
     top = np.sort(mi)[-2:]
-    if top[1] - top[0] > 2 * MI_TOL:
-        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+    check_ksg_argmax(got, cfg1.data, ia, ib, 10, MI_TOL, unique_ref=ref if top[1] - top[0] > 2 * MI_TOL else None)
 
 
 def test_region_max_planted_copy(ctx, pc, torch):
@@ -217,8 +215,8 @@ def test_region_max_planted_copy(ctx, pc, torch):
         got = ctx.corr_region_max(f, ra, rb, "pearson", prec)
         assert abs(got["value"] - 1.0) <= TOL[prec], (prec, got)
         # the copy is the unique argmax only where the top-2 gap exceeds the mode's error
-        if ref["value"] - ref["second"] > 2 * TOL[prec]:
-            assert (got["pa"], got["pb"]) == (p, q), (prec, got)
+        check_pearson_argmax(got, ref, e.data, e.regions[0].global_indices(e.nx, e.ny),
+                             e.regions[1].global_indices(e.nx, e.ny), TOL[prec])
     got = ctx.corr_region_max(f, ra, rb, "ksg", k=10)
     assert abs(got["value"] - (oracle.digamma_int(100) - oracle.digamma_int(10))) <= MI_TOL
     assert (got["pa"], got["pb"]) == (p, q)
@@ -235,11 +233,13 @@ def test_region_max_self_overlap(ctx, pc, torch, cfg1):
         got = ctx.corr_region_max(f, ra, ra, "pearson", prec)
         assert got["value"] < 0.999999 and abs(got["value"] - ref["value"]) <= TOL[prec]
         assert got["n_evaluated"] == ia.size * (ia.size - 1)
+        check_pearson_argmax(got, ref, cfg1.data, ia, ia, TOL[prec])
     ib = synth.Region(4, 0, 0, 8, 8, 4).global_indices(cfg1.nx, cfg1.ny)
     ref2 = oracle.pearson_region_max_matmul(cfg1.data, ia, ib)
     got2 = ctx.corr_region_max(f, ra, rpart, "pearson", "f32")
     assert abs(got2["value"] - ref2["value"]) <= 1e-5
     assert got2["n_evaluated"] == ref2["n_evaluated"]
+    check_pearson_argmax(got2, ref2, cfg1.data, ia, ib, 1e-5)
 
 
 def test_region_max_sampled_lists(ctx, pc, torch, cfg1):
@@ -254,6 +254,7 @@ def test_region_max_sampled_lists(ctx, pc, torch, cfg1):
     ref = oracle.region_max_from_values(r, la, lb, s[:, 0], s[:, 1], use_abs=True)
     got = ctx.corr_region_max(f, ra, rb, "pearson", "f32", samples=dev(torch, s))
     assert abs(got["value"] - ref["value"]) <= 1e-5 and got["n_evaluated"] == 3000
+    check_pearson_argmax(got, None, cfg1.data, s[:, 0], s[:, 1], 1e-5)
     mi, _ = oracle.ksg_pairs(cfg1.data, s, 10, want_counts=False)
     ref = oracle.region_max_from_values(mi, la, lb, s[:, 0], s[:, 1], use_abs=False)
     got = ctx.corr_region_max(f, ra, rb, "ksg", k=10, samples=dev(torch, s))
@@ -273,8 +274,7 @@ def test_cfg2_pearson_region_max(ctx, pc, torch, cfg2, prec):
     _say(f"  gpu {got['value']:.7f} oracle {ref['value']:.7f} second {ref['second']:.7f}")
     assert abs(got["value"] - ref["value"]) <= TOL[prec]
     assert got["n_evaluated"] == ia.size * ib.size == 419430400
-    if ref["value"] - ref["second"] > 2 * TOL[prec]:
-        assert (got["pa"], got["pb"]) == (ref["pa"], ref["pb"])
+    check_pearson_argmax(got, ref, cfg2.data, ia, ib, TOL[prec])
 
 
 _CFG2_REF = {}

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
+from argmax_checks import check_pearson_argmax
 import synth
 from oracle import aggregate_ref as AG
 
@@ -48,8 +49,8 @@ def _check(e_data, nx, ny, got, ra, sa, rb, sb, prec, data_b=None):
             g = got[i][j]
             assert abs(g["value"] - ref["value"]) <= TOL[prec], (prec, i, j, g, ref)
             assert g["n_evaluated"] == ref["n_evaluated"], (i, j, g["n_evaluated"], ref["n_evaluated"])
-            if ref["value"] - ref["second"] > 2 * TOL[prec]:
-                assert (g["pa"], g["pb"]) == (ref["pa"], ref["pb"]), (prec, i, j)
+            check_pearson_argmax(g, ref, e_data, ia, ib, TOL[prec], data_b=data_b,
+                                 same_field=data_b is None)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16", "f16x3"])
