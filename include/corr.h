@@ -28,6 +28,11 @@
  *  - One host thread at a time per corr_ctx; separate contexts may be used
  *    from separate threads. Calls run on the calling thread's current HIP
  *    device, which must be the device the context was created for.
+ *  - A context's workspaces serve one stream at a time: when a call names a
+ *    different stream than the previous call on the same context, the
+ *    library first synchronises the device (hipDeviceSynchronize), so work
+ *    on two streams never shares the workspaces while in flight. Use one
+ *    context per stream to overlap streams without that wait.
  *  - Point indices are global linear indices p = x + nx * (y + ny * z),
  *    int32. A region's local index follows the same x-fastest rule relative
  *    to its origin.
@@ -125,6 +130,16 @@ const char* corr_status_str(int status);
 
 /* Last error message of the calling thread ("" if none). */
 const char* corr_last_error(void);
+
+/*
+ * Cap on the device memory a context keeps in its grow-only workspaces (the
+ * sum over all of them), in bytes; 0 removes the cap (the default). A call
+ * whose workspaces would grow past the cap returns CORR_ENOMEM before its
+ * main kernel (kernels it enqueued up to that point wrote only into the
+ * context's own workspaces); the workspaces already held are kept. Prepared
+ * fields, BOS states and networks own their buffers and are not counted.
+ */
+int corr_set_workspace_limit(corr_ctx* ctx, size_t bytes);
 
 /*
  * Per-point statistics of every grid point of field A (Sec. 3.2: Pearson
@@ -267,7 +282,7 @@ int corr_tune_save(corr_ctx* ctx, const char* path);
 int corr_tune_load(corr_ctx* ctx, const char* path);
 
 /*
- * Sub-brick maxima: one level of brick refinement of a pair (Sec. 4, the
+ * Sub-brick maxima: one level of brick refinement of a pair (Sec. 3 and 4.2, the
  * focus view refines a selected brick pair). Brick ra is split into
  * splits_a[0] x splits_a[1] x splits_a[2] sub-bricks and rb into splits_b
  * likewise (each axis as evenly as possible, the first parts one cell
@@ -333,7 +348,7 @@ int corr_sampled_max(corr_ctx* ctx, const corr_field* A, const corr_field* B, co
 int corr_choose_strategy(int64_t na, int64_t nb, double pairs_per_s, double budget_s, int32_t* strategy);
 
 /*
- * One level of the mean tree (Sec. 4, sampling from spatial aggregates):
+ * One level of the mean tree (Sec. 3.3, sampling from spatial aggregates):
  * for every member m and every block of f x f x f grid points, the mean of
  * A's values over the block. Blocks tile the grid from the origin; a block on
  * a high face holds the min(f, n - f*X) points left on that axis and its

@@ -1,4 +1,4 @@
-"""Mean-tree aggregates (Sec. 4, sampling from spatial aggregates) --
+"""Mean-tree aggregates (Sec. 3.3, sampling from spatial aggregates) --
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 A mean-tree level with factor f stores, for every ensemble member and every
@@ -63,7 +63,7 @@ def mean_deviation(max_initial, max_level):
 def split_region(region, splits):
     """Sub-bricks of a brick (x0, y0, z0, dx, dy, dz) split into splits = (sx, sy, sz)
     parts per axis, as evenly as possible with the first parts one cell
-    larger; listed x-fastest. Brick refinement (Sec. 4) halves each axis,
+    larger; listed x-fastest. Brick refinement (Sec. 3) halves each axis,
     splits = (2, 2, 2)."""
     x0, y0, z0, dx, dy, dz = region
     axes = []

@@ -91,6 +91,10 @@ class Context:
     def set_timing(self, on: bool = True):
         _lib.check(self.L.corr_set_timing(self.h, 1 if on else 0))
 
+    def set_workspace_limit(self, nbytes: int):
+        """Cap the context's workspace memory (0: no cap); calls that need more return CORR_ENOMEM."""
+        _lib.check(self.L.corr_set_workspace_limit(self.h, int(nbytes)))
+
     def kernel_time_ms(self, which: str) -> float:
         ms = ctypes.c_float()
         _lib.check(self.L.corr_kernel_time_ms(self.h, self.KERNEL_CLASSES[which], ctypes.byref(ms)))

@@ -82,6 +82,7 @@ SIGNATURES = {
     "corr_tune_save": (_I, [_P, ctypes.c_char_p]),
     "corr_tune_load": (_I, [_P, ctypes.c_char_p]),
     "corr_set_timing": (_I, [_P, _I]),
+    "corr_set_workspace_limit": (_I, [_P, ctypes.c_size_t]),
     "bos_config_default": (None, [ctypes.POINTER(bos_config)]),
     "bos_create": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_field), ctypes.POINTER(corr_region),
                         _I32, _P, _I32, ctypes.POINTER(bos_config), ctypes.POINTER(_P), _P]),

@@ -1,4 +1,4 @@
-// Mean-tree levels (Sec. 4, sampling from spatial aggregates): per member,
+// Mean-tree levels (Sec. 3.3, sampling from spatial aggregates): per member,
 // the mean of the field over every f x f x f block of grid points.
 //
 // HBM-bound streaming reduction. One wavefront owns 64 consecutive x of one

@@ -50,9 +50,22 @@ int fail(int status, const std::string& msg) {
     return status;
 }
 
+int ctx_use_stream(corr_ctx* ctx, hipStream_t s) {
+    if (ctx->used && ctx->last_stream != s) CORR_HIP(hipDeviceSynchronize());
+    ctx->used = true;
+    ctx->last_stream = s;
+    return CORR_OK;
+}
+
 int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out) {
     if (bytes == 0) bytes = 256;
     if (ctx->ws_size[slot] < bytes) {
+        size_t others = 0;
+        for (int i = 0; i < WS_COUNT; ++i)
+            if (i != slot) others += ctx->ws_size[i];
+        if (bytes > ctx->ws_limit || others > ctx->ws_limit - bytes)
+            return fail(CORR_ENOMEM, "workspace limit: the call needs " + std::to_string(others + bytes) +
+                                         " bytes of context workspace, the limit is " + std::to_string(ctx->ws_limit));
         if (ctx->ws[slot]) {
             CORR_HIP(hipStreamSynchronize(stream));
             CORR_HIP(hipFree(ctx->ws[slot]));
@@ -60,6 +73,7 @@ int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out
             ctx->ws_size[slot] = 0;
         }
         size_t want = bytes + bytes / 8;
+        if (want > ctx->ws_limit - others) want = bytes;
         hipError_t e = hipMalloc(&ctx->ws[slot], want);
         if (e != hipSuccess) {
             ctx->ws[slot] = nullptr;
@@ -450,6 +464,12 @@ void corr_destroy(corr_ctx* c) {
     delete c;
 }
 
+int corr_set_workspace_limit(corr_ctx* ctx, size_t bytes) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    ctx->ws_limit = bytes == 0 ? (size_t)-1 : bytes;
+    return CORR_OK;
+}
+
 int corr_set_timing(corr_ctx* ctx, int on) {
     if (!ctx) return fail(CORR_EINVAL, "null context");
     ctx->timing = on != 0;
@@ -481,6 +501,7 @@ int corr_autotune(corr_ctx* ctx, const corr_field* A, const corr_region* ra, con
     if (best_ms) *best_ms = -1.0f;
     if (A->M > 128) return CORR_OK;  // the chunked contraction has a single configuration
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
     if (ba.count() * bb.count() >= (int64_t(1) << 31))
         return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
@@ -528,6 +549,7 @@ int corr_ksg_autotune(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     std::vector<float> out_host;  // unused; results go to a workspace
     void* mi = nullptr;
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_ = ctx_use_stream(ctx, s)) return rc_;
     int rc = ws_get(ctx, WS_PAIRS, sizeof(float) * (size_t)n, s, &mi);
     if (rc) return rc;
     const bool saved_timing = ctx->timing;
@@ -612,6 +634,7 @@ int corr_standardize(corr_ctx* ctx, const corr_field* A, float* mu32, float* inv
     int rc = check_field(A, "A");
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     Box box = whole_box(*A);
     const int64_t n = box.count();
     void* sb = nullptr;
@@ -638,6 +661,7 @@ int corr_pearson_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, 
     if (n == 0) return CORR_OK;
     if (!pairs || !r_out) return fail(CORR_EINVAL, "null pairs or output");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     const int64_t ld = round_up(A->M, 16);
     const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
     Box ba = whole_box(*A), bb = whole_box(*B);
@@ -675,6 +699,7 @@ int corr_ksg_mi_pairs(corr_ctx* ctx, const corr_field* A, const corr_field* B, c
     if (n == 0) return CORR_OK;
     if (!pairs || (!mi_out && !counts_out)) return fail(CORR_EINVAL, "null pairs or outputs");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     const bool raw = flags & CORR_KSG_RAW;
     const int fmt = raw ? ZF_RAW : ZF_KSG;
     const int64_t ld = round_up(A->M, 4);
@@ -767,6 +792,7 @@ int corr_prepare(corr_ctx* ctx, const corr_field* A, int measure, int prec, corr
         return fail(CORR_EUNSUPPORTED, "unknown precision");
     if (measure == CORR_KSG && A->M > 2048) return fail(CORR_EUNSUPPORTED, "M > 2048");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     corr_prepared* p = new (std::nothrow) corr_prepared();
     if (!p) return fail(CORR_ENOMEM, "corr_prepare: host allocation failed");
     p->device = ctx->device;
@@ -811,6 +837,7 @@ int corr_pearson_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const cor
     if (n == 0) return CORR_OK;
     if (!pairs || !r_out) return fail(CORR_EINVAL, "null pairs or output");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_ = ctx_use_stream(ctx, s)) return rc_;
     timing_begin(ctx, TK_PAIRS, s);
     int rc = launch_pearson_pairs(A->prec, A->hi, A->lo, B->hi, B->lo, A->ld, pairs, n, r_out, prepared_box(A),
                                   prepared_box(B), 0, nullptr, s);
@@ -831,6 +858,7 @@ int corr_ksg_mi_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr
     if (n == 0) return CORR_OK;
     if (!pairs || (!mi_out && !counts_out)) return fail(CORR_EINVAL, "null pairs or outputs");
     hipStream_t s = (hipStream_t)stream;
+    if (int rc_ = ctx_use_stream(ctx, s)) return rc_;
     KsgArgs a{};
     a.za = (const float*)A->hi;
     a.zb = (const float*)B->hi;
@@ -890,6 +918,7 @@ static int region_max_impl(Ws& w, const corr_field* A, const corr_region* ra, co
     Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
     const int64_t na = ba.count(), nb = bb.count();
     if (na * nb >= (int64_t(1) << 31)) return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     const bool sf = same_field(*A, *B);
     memset(out, 0, sizeof(*out));
     out->pa = out->pb = -1;
@@ -994,6 +1023,7 @@ int corr_block_means(corr_ctx* ctx, const corr_field* A, int f, int out_dtype, v
     const int64_t nout = (int64_t)((A->nx + f - 1) / f) * ((A->ny + f - 1) / f) * ((A->nz + f - 1) / f);
     if (out_stride != 0 && out_stride < nout) return fail(CORR_EINVAL, "out_stride smaller than the level's grid");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     timing_begin(ctx, TK_AGG, s);
     rc = launch_block_means(*A, f, out_dtype, out, out_stride, s);
     timing_end(ctx, TK_AGG, s);
@@ -1026,7 +1056,9 @@ static int stage_samples(corr_ctx* ctx, const corr_field* A, const corr_field* B
                          int32_t* out, hipStream_t s) {
     const size_t bb = sample_boxes_bytes(n_pairs);
     void* dbox = nullptr;
-    int rc = ws_get(ctx, WS_SBOXES, bb + sizeof(corr_max) * (size_t)n_pairs, s, &dbox);
+    int rc = ctx_use_stream(ctx, s);
+    if (rc) return rc;
+    rc = ws_get(ctx, WS_SBOXES, bb + sizeof(corr_max) * (size_t)n_pairs, s, &dbox);
     if (rc) return rc;
     std::vector<unsigned char> hbox(bb);
     fill_sample_boxes(hbox.data(), regions, region_pairs, n_pairs, *A, *B);
@@ -1061,6 +1093,7 @@ int corr_sampled_max(corr_ctx* ctx, const corr_field* A, const corr_field* B, co
     if (n_pairs == 0) return CORR_OK;
     if (!out) return fail(CORR_EINVAL, "null output");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     const int64_t n = (int64_t)n_pairs * n_samples;
     void *dpairs = nullptr, *dvals = nullptr, *dbox = nullptr;
     if ((rc = ws_get(ctx, WS_SAMPLES, sizeof(int32_t) * 2 * (size_t)(n > 0 ? n : 1), s, &dpairs))) return rc;
@@ -1139,6 +1172,7 @@ int corr_region_submax(corr_ctx* ctx, const corr_field* A, const corr_region* ra
     if (sa[0].count() * sb[0].count() >= (int64_t(1) << 31))  // the first sub-bricks are the largest
         return fail(CORR_EUNSUPPORTED, "a sub-brick pair has 2^31 or more point pairs");
     hipStream_t s = (hipStream_t)stream;
+    if ((rc = ctx_use_stream(ctx, s))) return rc;
     const bool sf = same_field(*A, *B);
     const bool acc64 = stats_acc64(CORR_PEARSON, A->M);
     const int fmt = zfmt_for_prec(prec);

@@ -121,6 +121,9 @@ struct corr_ctx {
     unsigned long long* keys = nullptr;     // device scratch for max keys
     unsigned long long* keys_host = nullptr;  // pinned host mirror
     void* scratch = nullptr;  // device address of this GPU's fixed scratch (no-allocation calls)
+    size_t ws_limit = (size_t)-1;  // cap on the sum of the workspace slots (corr_set_workspace_limit)
+    hipStream_t last_stream = nullptr;  // stream of the previous call that used the context's buffers
+    bool used = false;
     // kernel timing hook: events per kernel class (see corr_set_timing)
     bool timing = false;
     hipEvent_t ev_start[5] = {};
@@ -132,6 +135,12 @@ namespace corr {
 
 // Grow-only workspace buffer; synchronises `stream` before replacing a buffer.
 int ws_get(corr_ctx* ctx, int slot, size_t bytes, hipStream_t stream, void** out);
+
+// Orders a call on `s` after the context's previous call: when the stream
+// differs from the previous call's, the device is synchronised first, so two
+// streams never use the context's workspaces at the same time.
+int ctx_use_stream(corr_ctx* ctx, hipStream_t s);
+
 
 // ---- statistics layout ------------------------------------------------------
 // Per point of a point set, four float arrays of length n (contiguous):

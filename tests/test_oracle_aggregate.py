@@ -1,4 +1,4 @@
-"""Pins of the mean-tree oracle (Sec. 4, sampling from spatial aggregates):
+"""Pins of the mean-tree oracle (Sec. 3.3, sampling from spatial aggregates):
 a pure-Python loop over global indices on tiny ragged grids, the closed form
 for fields linear in x, y, z (a block's mean is the value at the centre of
 the points it holds), conservation of the member total, the tree property
