@@ -169,14 +169,17 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
-    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree", "meantree-dev", "samplers"],
+    ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree", "meantree-dev", "samplers",
+                             "proposal"],
                     help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
                          "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates; onetoall: one "
                          "reference point against every point of a 250x352x20 field (M=100) and of the "
                          "128x128x32 field (M=1000); meantree: mean-tree levels f=2,4 of a 180-member "
                          "640x704x64 field; meantree-dev: deviation of brick maxima on those levels over the 3828 "
                          "brick pairs of the 352x256x20 field; samplers: convergence of uniform / Halton / plastic "
-                         "sampled maxima over those pairs and on 6-D Gaussian test objectives")
+                         "sampled maxima over those pairs and on 6-D Gaussian test objectives; proposal: the "
+                         "learned BOS proposal trained on ten 88-region context fields and judged on two unseen "
+                         "ones against plain BOS and exhaustive maxima")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
@@ -207,6 +210,8 @@ def main():
         return run_meantree_dev(args, torch, synth, pc)
     if args.workload == "samplers":
         return run_samplers(args, torch, synth, pc)
+    if args.workload == "proposal":
+        return run_proposal(args, torch, synth, pc)
     return run_focus(args, torch, synth, pc)
 
 
@@ -791,6 +796,111 @@ def large_legs(args, torch, synth, pc):
     del f, pairs, out
     torch.cuda.empty_cache()
     return legs
+
+
+def run_proposal(args, torch, synth, pc):
+    """Learned BOS proposal at scale: records from ten context fields of the
+    352x256x20 generator (seeds 1000-1009, 88 regions, 3828 pairs each), the
+    58 -> 256 -> 256 -> 18 network trained on the GPU, then on two unseen
+    fields (seeds 2000, 2001) plain GPU BOS at 100 samples per pair against
+    GPU BOS seeded with the network's best candidate at 36 and 100 samples,
+    each judged by the exhaustive FP16x3 maxima, planted and noise pairs apart.
+    One step is one learned-proposal view at 36 samples per pair: inputs,
+    inference, prior cells and the batched BOS."""
+    from paper_2309_03308_amd import proposal as PR
+    ctx = pc.Context(0)
+    Xs, Ys = [], []
+    t0 = time.perf_counter()
+    for s in range(1000, 1010):
+        e = synth.make_cfg3(seed=s)
+        f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+        regs = [pc.region(*r.as_tuple()) for r in e.regions]
+        x, y, _ = PR.make_records(ctx, f, regs, synth.region_pair_list(len(e.regions)))
+        Xs.append(x)
+        Ys.append(y)
+        print(f"proposal: records of field {s}: {x.shape[0]}", file=sys.stderr, flush=True)
+        del f
+    t_rec = time.perf_counter() - t0
+    X, Y = torch.cat(Xs), torch.cat(Ys)
+    net = pc.PropMlp(ctx, X.shape[1], 256, PR.n_out(), seed=1)
+    t0 = time.perf_counter()
+    epochs = 50
+    hist = PR.train(net, X, Y, epochs=epochs, batch=256, lr=1e-3, wd=1e-4, loss_w=PR.loss_weights())
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"proposal: trained on {X.shape[0]} records in {t_train:.1f} s", file=sys.stderr, flush=True)
+    evals = {}
+    view_ms = []
+    for s in (2000, 2001):
+        e = synth.make_cfg3(seed=s)
+        f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+        regs = [pc.region(*r.as_tuple()) for r in e.regions]
+        pairs = synth.region_pair_list(len(e.regions))
+        truth = np.array([ctx.corr_region_max(f, regs[a], regs[b], "pearson", "f16x3")["value"] for a, b in pairs])
+        planted = np.zeros(len(pairs), bool)
+        for gr in e.groups:
+            rs = set(gr["regions"])
+            planted |= np.array([(a in rs and b in rs) for a, b in pairs])
+        for name, nt, learned in (("plain100", 100, False), ("learned36", 36, True), ("learned100", 100, True),
+                                  ("plain36", 36, False)):
+            PR.run_bos(ctx, f, regs, pairs, n_total=nt, seed=7)  # warm-up (kernels, graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prior = None
+            if learned:
+                x, hot = PR.inputs(ctx, f, regs, pairs)
+                _, prior = PR.prior_cells(net, x, hot, regs, pairs, e.nx, e.ny)
+            vals, nev = PR.run_bos(ctx, f, regs, pairs, prior=prior, n_total=nt, seed=7)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if name == "learned36":
+                view_ms.append(dt * 1e3)
+            err = np.abs(truth - vals)
+            r = evals.setdefault(name, {"mean_abs_err": [], "planted_mean_abs_err": [], "noise_mean_abs_err": [],
+                                        "planted_frac_within_0.01": [], "evaluations": [], "view_ms": []})
+            r["mean_abs_err"].append(float(err.mean()))
+            r["planted_mean_abs_err"].append(float(err[planted].mean()))
+            r["noise_mean_abs_err"].append(float(err[~planted].mean()))
+            r["planted_frac_within_0.01"].append(float(np.mean(err[planted] <= 0.01)))
+            r["evaluations"].append(int(nev.sum()))
+            r["view_ms"].append(dt * 1e3)
+        print(f"proposal: evaluated field {s} ({int(planted.sum())} planted pairs)", file=sys.stderr, flush=True)
+        del f
+    summary = {k: {m: float(np.mean(v)) for m, v in r.items()} for k, r in evals.items()}
+    ms = float(np.mean(view_ms))
+    n36 = summary["learned36"]["evaluations"]
+    extra = {"breakdown": {"training_records": int(X.shape[0]), "record_generation_s": t_rec,
+                           "training_s": t_train, "epochs": epochs, "loss_first_last": [hist[0], hist[-1]],
+                           "unseen_fields": 2, "per_config": summary, "per_field": evals}}
+    if not args.no_cpu_baseline:
+        from oracle import mlp_ref
+        n_in, H, n_o = X.shape[1], 256, PR.n_out()
+        params = net.get_params().astype(np.float64)
+        xb = X[:64].cpu().numpy().astype(np.float64)
+        yb = Y[:64].cpu().numpy().astype(np.float64)
+        w = np.array(PR.loss_weights(), np.float64)
+        reps = 20
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):  # one core: the BLAS calls of the oracle run single-threaded
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                mlp_ref.loss_and_grad(params, xb, yb, w, n_in, H, n_o)
+            t_cpu = (time.perf_counter() - t0) / reps
+        extra["cpu_baseline"] = {"value": 64 / t_cpu, "unit": "training samples/s (forward + backward)",
+                                 "cores": 1, "kind": "oracle",
+                                 "sample": f"FP64 NumPy MLP forward and backward on a 64-record batch, {reps} reps "
+                                           f"({t_cpu * 1e3:.2f} ms each)"}
+        extra["gpu_training_samples_per_s"] = X.shape[0] * epochs / t_train
+    line = _line(args, n36 / (ms / 1e3), ms,
+                 {"workload": "learned BOS proposal: trained on 10 context fields (352x256x20, 88 regions, M=100, "
+                              "seeds 1000-1009), judged on 2 unseen fields (seeds 2000-2001); step = one "
+                              "learned-proposal view at 36 samples per pair", "members": 100,
+                  "region_pairs": 3828, "network": "58-256-256-18 SiLU, BF16-rounded weights, FP32"}, **extra)
+    line["unit"] = "evaluated point pairs/s"
+    line["steps"], line["warmup"] = 2, 1
+    print(json.dumps(line), flush=True)
+    net.close()
+    ctx.close()
 
 
 def run_focus(args, torch, synth, pc):

@@ -199,6 +199,20 @@ int corr_prepare(corr_ctx* ctx, const corr_field* A, int measure, int prec, corr
 void corr_prepared_destroy(corr_prepared* p);
 
 /*
+ * Exhaustive Pearson maxima of many small box pairs in one call (Sec. 3, the
+ * brick-pair indicator, for boxes of up to 4096 points each, e.g. the
+ * neighbourhoods of candidate cells). For box pair t: the maximum |r| over
+ * (pA, pB) in boxes_a[t] x boxes_b[t], with the signed r, the argmax (the
+ * smallest local index la * |b| + lb among equal values) and n_evaluated, as
+ * corr_region_max returns them; pA == pB is skipped when A and B are the same
+ * handle. A and B: prepared for CORR_PEARSON with CORR_PREC_F32 (else
+ * CORR_EUNSUPPORTED). boxes_a, boxes_b: HOST corr_region [n] inside the
+ * fields' grids; out: HOST corr_max [n]. Synchronises `stream`.
+ */
+int corr_box_pairs_max(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B, const corr_region* boxes_a,
+                       const corr_region* boxes_b, int32_t n, corr_max* out, corr_stream_t stream);
+
+/*
  * corr_pearson_pairs on prepared fields: A and B (may be the same handle)
  * prepared for CORR_PEARSON with the same member count and precision; the
  * results equal corr_pearson_pairs with that precision bit for bit.

@@ -186,6 +186,19 @@ class Context:
                                                      _stream_ptr(stream)))
         return (mi, cnt) if counts else mi
 
+    def corr_box_pairs_max(self, A: "Prepared", boxes_a, boxes_b, B: "Prepared" = None, stream=None) -> list:
+        """Exhaustive max |r| of many small box pairs (fields prepared with pearson / f32)."""
+        B = A if B is None else B
+        n = len(boxes_a)
+        if len(boxes_b) != n:
+            raise ValueError("boxes_a and boxes_b differ in length")
+        ba = (corr_region * max(n, 1))(*[b if isinstance(b, corr_region) else region(*b) for b in boxes_a])
+        bb = (corr_region * max(n, 1))(*[b if isinstance(b, corr_region) else region(*b) for b in boxes_b])
+        out = (corr_max * max(n, 1))()
+        _lib.check(self.L.corr_box_pairs_max(self.h, A.h, B.h, ba, bb, n, out, _stream_ptr(stream)))
+        return [dict(value=o.value, signed_value=o.signed_value, pa=o.pa, pb=o.pb, n_evaluated=o.n_evaluated)
+                for o in out[:n]]
+
     def corr_region_max(self, A: Field, ra: corr_region, rb: corr_region, measure="pearson", prec="f16", k=10,
                         B: Field = None, samples=None, stream=None) -> dict:
         return self._region_max(self.L.corr_region_max, A, ra, rb, measure, prec, k, B, samples, stream)

@@ -70,6 +70,7 @@ SIGNATURES = {
                              ctypes.POINTER(corr_region), _I, _I, _I32, _P, _I64, ctypes.POINTER(corr_max), _P]),
     "corr_prepare": (_I, [_P, ctypes.POINTER(corr_field), _I, _I, ctypes.POINTER(_P), _P]),
     "corr_prepared_destroy": (None, [_P]),
+    "corr_box_pairs_max": (_I, [_P, _P, _P, _P, _P, _I32, _P, _P]),
     "corr_pearson_pairs_prepared": (_I, [_P, _P, _P, _P, _I64, _P, _P]),
     "corr_ksg_mi_pairs_prepared": (_I, [_P, _P, _P, _P, _I64, _I32, _P, _P, _P]),
     "corr_region_max_noalloc": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region),

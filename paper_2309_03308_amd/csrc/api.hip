@@ -888,6 +888,59 @@ int corr_ksg_mi_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr
     return rc;
 }
 
+int corr_box_pairs_max(corr_ctx* ctx, const corr_prepared* A, const corr_prepared* B, const corr_region* boxes_a,
+                       const corr_region* boxes_b, int32_t n, corr_max* out, corr_stream_t stream) {
+    if (!ctx) return fail(CORR_EINVAL, "null context");
+    if (!A || !B) return fail(CORR_EINVAL, "null prepared field");
+    if (n < 0) return fail(CORR_EINVAL, "n < 0");
+    if (n == 0) return CORR_OK;
+    if (!boxes_a || !boxes_b || !out) return fail(CORR_EINVAL, "null boxes or output");
+    if (A->measure != CORR_PEARSON || B->measure != CORR_PEARSON || A->prec != CORR_PREC_F32 ||
+        B->prec != CORR_PREC_F32)
+        return fail(CORR_EUNSUPPORTED, "box maxima need fields prepared for Pearson with CORR_PREC_F32");
+    if (A->M != B->M) return fail(CORR_EINVAL, "fields differ in M");
+    std::vector<Box> hb(2 * (size_t)n);
+    int64_t max_pts = 1;
+    for (int32_t t = 0; t < n; ++t) {
+        const corr_region* rs[2] = {&boxes_a[t], &boxes_b[t]};
+        const corr_prepared* fs[2] = {A, B};
+        for (int q = 0; q < 2; ++q) {
+            const corr_region& r = *rs[q];
+            const corr_prepared& f = *fs[q];
+            if (r.dx < 1 || r.dy < 1 || r.dz < 1 || r.x0 < 0 || r.y0 < 0 || r.z0 < 0 || r.x0 + r.dx > f.nx ||
+                r.y0 + r.dy > f.ny || r.z0 + r.dz > f.nz)
+                return fail(CORR_EINVAL, "box " + std::to_string(t) + " empty or outside the grid");
+            const int64_t c = (int64_t)r.dx * r.dy * r.dz;
+            if (c > 4096) return fail(CORR_EUNSUPPORTED, "box maxima: a box holds more than 4096 points");
+            max_pts = std::max(max_pts, c);
+            hb[(size_t)q * n + t] = Box{r.x0, r.y0, r.z0, r.dx, r.dy, r.dz, f.nx, f.ny};
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ctx_use_stream(ctx, s);
+    if (rc) return rc;
+    void *dbox = nullptr, *dkeys = nullptr;
+    if ((rc = ws_get(ctx, WS_BOXES, sizeof(Box) * hb.size(), s, &dbox))) return rc;
+    if ((rc = ws_get(ctx, WS_BOX_KEYS, sizeof(unsigned long long) * (size_t)n, s, &dkeys))) return rc;
+    CORR_HIP(hipMemcpyAsync(dbox, hb.data(), sizeof(Box) * hb.size(), hipMemcpyHostToDevice, s));
+    const bool same = A == B;
+    timing_begin(ctx, TK_PAIRS, s);
+    rc = launch_box_pairs_max((const float*)A->hi, (const float*)B->hi, A->ld, (const Box*)dbox, n, same ? 1 : 0,
+                              (int)max_pts, (unsigned long long*)dkeys, ctx->num_cus, s);
+    timing_end(ctx, TK_PAIRS, s);
+    if (rc) return rc;
+    std::vector<unsigned long long> keys((size_t)n);
+    CORR_HIP(hipMemcpyAsync(keys.data(), dkeys, sizeof(unsigned long long) * (size_t)n, hipMemcpyDeviceToHost, s));
+    CORR_HIP(hipStreamSynchronize(s));
+    for (int32_t t = 0; t < n; ++t) {
+        const Box& ba = hb[t];
+        const Box& bb = hb[(size_t)n + t];
+        decode_key(keys[t], ba, bb, true, &out[t]);
+        out[t].n_evaluated = ba.count() * bb.count() - (same ? overlap_count(ba, bb) : 0);
+    }
+    return CORR_OK;
+}
+
 }  // extern "C"
 
 // Region maximum (exhaustive Pearson, or Pearson / KSG over a sample list)

@@ -93,7 +93,7 @@ __host__ __device__ inline int64_t box_local_fast(const Box& b, const FastDiv& d
 enum WsSlot {
     WS_STATS_A = 0, WS_STATS_B, WS_Z_A, WS_Z_B, WS_ZH_A, WS_ZH_B, WS_ZL_A, WS_ZL_B,
     WS_PAIRS, WS_MISC, WS_SORT_A, WS_SORT_B, WS_SAMPLES, WS_SVALUES, WS_SBOXES,
-    WS_SUB_AH, WS_SUB_AL, WS_SUB_BH, WS_SUB_BL, WS_SUB_KEYS, WS_COUNT
+    WS_SUB_AH, WS_SUB_AL, WS_SUB_BH, WS_SUB_BL, WS_SUB_KEYS, WS_BOXES, WS_BOX_KEYS, WS_COUNT
 };
 
 }  // namespace corr
@@ -171,6 +171,10 @@ size_t prec_elem_bytes(int prec);
 // pairs.hip
 // Rows of za/zb are the local indices of the boxes (a whole-grid box makes
 // them global indices). key (may be NULL) receives the fused max of |r|.
+// Exhaustive max |r| of each of n box pairs (boxes [A boxes n][B boxes n],
+// device); keys[t] receives the orderable key of pair t (0: nothing evaluated).
+int launch_box_pairs_max(const float* za, const float* zb, int64_t ld, const Box* boxes, int n, int same_field,
+                         int max_points, unsigned long long* keys, int num_cus, hipStream_t s);
 int launch_pearson_pairs(int prec, const void* za_hi, const void* za_lo, const void* zb_hi, const void* zb_lo,
                          int64_t ld, const int32_t* pairs, int64_t n, float* r_out, const Box& ba, const Box& bb,
                          int same_field, unsigned long long* key, hipStream_t s);

@@ -4,6 +4,8 @@
 // mean_p)^2) (point-major, members contiguous), r = sum_m Zhat[a][m] Zhat[b][m].
 // A pair has no operand reuse, so this is a gather: G lanes per pair stream
 // the two rows with 16-byte loads and reduce with cross-lane shuffles.
+#include <algorithm>
+
 #include "common.h"
 
 namespace corr {
@@ -141,6 +143,87 @@ int launch_pearson_pairs(int prec, const void* za_hi, const void* za_lo, const v
         case CORR_PREC_F16X3: launch_pp<CORR_PREC_F16X3>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
         case CORR_PREC_BF16X3: launch_pp<CORR_PREC_BF16X3>(G, grid, ah, al, bh, bl, ld_vec, pairs, n, r_out, ba, bb, same_field, key, s); break;
     }
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+}  // namespace corr
+
+namespace corr {
+
+// Exhaustive maxima of many small box pairs (Sec. 3, the brick-pair
+// indicator): one workgroup per box pair. The A box's FP32 standardised rows
+// are staged in LDS (in chunks of rows when they do not all fit); each
+// thread takes (i, j) items with a stride of 256, reads B row j from global
+// memory (the B box's rows stay in L1/L2 for the workgroup's lifetime) and
+// keeps the largest key (|r|, smallest local index, sign). The workgroup's
+// keys meet in one LDS reduction; no atomics.
+__global__ __launch_bounds__(256) void box_pairs_max_kernel(const float* __restrict__ za, const float* __restrict__ zb,
+                                                            int64_t ld, const Box* __restrict__ boxes, int n,
+                                                            int same_field, int rows_lds,
+                                                            unsigned long long* __restrict__ keys) {
+    extern __shared__ __attribute__((aligned(16))) float sa[];
+    __shared__ unsigned long long red[256];
+    const int tid = threadIdx.x;
+    const int nv = (int)(ld / 4);
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const Box A = boxes[t], B = boxes[n + t];
+        // bounds of the loops that hold barriers: wave-uniform by construction
+        const int na = __builtin_amdgcn_readfirstlane((int)A.count());
+        const int nb = __builtin_amdgcn_readfirstlane((int)B.count());
+        unsigned long long best = 0;
+        for (int a0 = 0; a0 < na; a0 += rows_lds) {
+            const int rows = __builtin_amdgcn_readfirstlane(min(rows_lds, na - a0));
+            __syncthreads();  // the previous chunk's readers are done
+            for (int v = tid; v < rows * nv; v += 256) {
+                const int i = v / nv, c = v - i * nv;
+                reinterpret_cast<float4*>(sa)[v] =
+                    reinterpret_cast<const float4*>(za + (int64_t)A.global(a0 + i) * ld)[c];
+            }
+            __syncthreads();
+            for (int q = tid; q < rows * nb; q += 256) {
+                const int i = q / nb, j = q - i * nb;
+                const int32_t pa = A.global(a0 + i), pb = B.global(j);
+                if (same_field && pa == pb) continue;
+                const float4* ra = reinterpret_cast<const float4*>(sa) + (int64_t)i * nv;
+                const float4* rb = reinterpret_cast<const float4*>(zb + (int64_t)pb * ld);
+                float s = 0.0f;
+                for (int c = 0; c < nv; ++c) {
+                    const float4 x = ra[c], y = rb[c];
+                    s = fmaf(x.x, y.x, s);
+                    s = fmaf(x.y, y.y, s);
+                    s = fmaf(x.z, y.z, s);
+                    s = fmaf(x.w, y.w, s);
+                }
+                s = fminf(1.0f, fmaxf(-1.0f, s));
+                const unsigned long long key =
+                    make_key(fabsf(s), (uint32_t)(a0 + i) * (uint32_t)nb + (uint32_t)j, s < 0.0f ? 1u : 0u);
+                best = key > best ? key : best;
+            }
+        }
+        red[tid] = best;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (tid < w) red[tid] = red[tid + w] > red[tid] ? red[tid + w] : red[tid];
+            __syncthreads();
+        }
+        if (tid == 0) keys[t] = red[0];
+        __syncthreads();  // red is rewritten by the next box pair
+    }
+}
+
+int launch_box_pairs_max(const float* za, const float* zb, int64_t ld, const Box* boxes, int n, int same_field,
+                         int max_points, unsigned long long* keys, int num_cus, hipStream_t s) {
+    if (n <= 0) return CORR_OK;
+    if (ld % 4) return fail(CORR_EINVAL, "box maxima: row stride must be a multiple of 4");
+    // LDS budget 48 KiB for A rows
+    int rows_lds = (int)std::min<int64_t>(max_points, (48 * 1024) / (ld * 4));
+    if (rows_lds < 1) return fail(CORR_EUNSUPPORTED, "box maxima: member rows too long for the LDS stage");
+    const size_t lds = (size_t)rows_lds * ld * 4;
+    int rc = kernel_setup((const void*)box_pairs_max_kernel, lds, 256, nullptr);
+    if (rc) return rc;
+    const int grid = (int)std::min<int64_t>(n, (int64_t)num_cus * 8);
+    box_pairs_max_kernel<<<dim3((unsigned)grid), 256, lds, s>>>(za, zb, ld, boxes, n, same_field, rows_lds, keys);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }

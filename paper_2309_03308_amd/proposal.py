@@ -10,9 +10,10 @@ pick of the other) are mapped by the proposal network (PropMlp) to
 The candidate with the largest predicted neighbourhood maximum seeds batched
 BOS (Sec. 3.1) as its first initial sample (bos_set_prior); plain BOS and
 exhaustive search stay the reference for its error. Records come from the
-method itself: exhaustive region maxima (corr_region_max) over the whole pair
-and over each candidate's neighbourhood boxes give the labels; MI labels are
-optional (weighted out of the loss when absent).
+method itself: exhaustive region maxima over the whole pair (corr_region_max)
+and over every candidate's neighbourhood box pair (one corr_box_pairs_max call
+per field) give the labels; MI labels are optional (weighted out of the loss
+when absent).
 
 Every numeric step runs in the library's kernels; this module only moves
 rows between calls and converts picks into cell indices.
@@ -57,14 +58,23 @@ def make_records(ctx: Context, A: Field, regions, region_pairs, mi_values=None, 
     rp = np.asarray(region_pairs, np.int32).reshape(-1, 2)
     x, hot = inputs(ctx, A, regs, rp, n_hot, D, r_nms)
     y = np.zeros((rp.shape[0], n_out(n_hot)), np.float32)
+    boxes_a, boxes_b = [], []
     for k, (a, b) in enumerate(rp):
         ra, rb = regs[a], regs[b]
         y[k, 0] = ctx.corr_region_max(A, ra, rb, "pearson", prec)["value"]
+        nb_a = [_nbhd(_local(int(hot[a, i]), ra, A.nx, A.ny), ra, radius) for i in range(n_hot)]
+        nb_b = [_nbhd(_local(int(hot[b, j]), rb, A.nx, A.ny), rb, radius) for j in range(n_hot)]
         for i in range(n_hot):
-            ba = _nbhd(_local(int(hot[a, i]), ra, A.nx, A.ny), ra, radius)
             for j in range(n_hot):
-                bb = _nbhd(_local(int(hot[b, j]), rb, A.nx, A.ny), rb, radius)
-                y[k, 2 + i * n_hot + j] = ctx.corr_region_max(A, ba, bb, "pearson", prec)["value"]
+                boxes_a.append(nb_a[i])
+                boxes_b.append(nb_b[j])
+    # every candidate neighbourhood pair of the field in one batched call
+    prep = ctx.corr_prepare(A, "pearson", "f32")
+    try:
+        nbv = ctx.corr_box_pairs_max(prep, boxes_a, boxes_b)
+    finally:
+        prep.close()
+    y[:, 2:] = np.array([r["value"] for r in nbv], np.float32).reshape(rp.shape[0], n_hot * n_hot)
     if mi_values is not None:
         y[:, 1] = np.asarray(mi_values, np.float32)
     return x, torch.from_numpy(y).to(x.device), hot
