@@ -2,7 +2,7 @@
 //
 // One persistent kernel per iteration. The host knows every pair's batch
 // schedule (it is drawn from the seed) and lists, per iteration, the pairs
-// that still sample there, costliest first; workgroups (256 threads) walk
+// that still sample there, costliest first; workgroups (512 threads) walk
 // that list with a static stride, so the loop over pairs, like every loop
 // that contains a barrier, runs on wave-uniform (scalar) values. For a pair
 // the workgroup
@@ -45,6 +45,13 @@
 #include "common.h"
 
 namespace corr {
+
+// Threads per workgroup (one pair at a time): one candidate per thread at the
+// default 512 candidates, two waves per SIMD.
+constexpr int BT = 512;
+constexpr int NW = BT / 64;
+// Rows of the triangular solve handled per pass over the stored solve vectors.
+constexpr int SOLVE_R = 8;
 
 __device__ inline double ph_gauss(uint64_t seed, uint64_t pair, uint64_t stream, uint64_t index, uint64_t axis) {
     uint64_t o[4];
@@ -220,7 +227,7 @@ __device__ void eval_cells(const BosDev& d, int pair, const int* cells6, int nce
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const Box A = d.ba[pair], B = d.bb[pair];
     const int slot_f = 2 * ((d.M + 1) & ~1) + 2 * d.p2;
-    for (int m = wave; m < ncell; m += 4) {
+    for (int m = wave; m < ncell; m += NW) {
         const int* c = cells6 + 6 * m;
         float sgn;
         const float v = wave_objective<KP1>(d, cell_point_a(A, c), cell_point_b(B, c), stage + wave * slot_f, &sgn);
@@ -249,7 +256,7 @@ __device__ int block_argmax(double v, int idx, double* red_v, int* red_i) {
     red_v[tid] = v;
     red_i[tid] = idx;
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
+    for (int s = BT / 2; s >= 1; s >>= 1) {
         if (tid < s) {
             const double ov = red_v[tid + s];
             const int oi = red_i[tid + s];
@@ -275,7 +282,7 @@ __device__ void bos_init_pair(const BosDev& d, int pair, double* sm) {
     double* vals = sm + d.off_y;
     float* svals = reinterpret_cast<float*>(sm + d.off_a);
     const Box A = d.ba[pair], B = d.bb[pair];
-    for (int s = tid; s < d.n_init; s += 256) {
+    for (int s = tid; s < d.n_init; s += BT) {
         for (int a = 0; a < 6; ++a) {
             const int dim = axis_dim(A, B, a);
             int c = (int)(ph_uniform(d.seed, pair, ST_INIT, s, a) * dim);
@@ -290,7 +297,7 @@ __device__ void bos_init_pair(const BosDev& d, int pair, double* sm) {
         }
     }
     __syncthreads();
-    for (int s = tid; s < d.n_init; s += 256) {
+    for (int s = tid; s < d.n_init; s += BT) {
         int is_dup = 0;
         for (int t = 0; t < s && !is_dup; ++t) {
             bool same = true;
@@ -314,7 +321,7 @@ __device__ void bos_init_pair(const BosDev& d, int pair, double* sm) {
     eval_cells<KP1>(d, pair, uniq, n, vals, svals, reinterpret_cast<float*>(sm + d.off_th));
     __syncthreads();
     const int base = pair * d.n_total;
-    for (int m = tid; m < n; m += 256) {
+    for (int m = tid; m < n; m += BT) {
         for (int a = 0; a < 6; ++a) d.cells[(int64_t)(base + m) * 6 + a] = (int16_t)uniq[6 * m + a];
         d.yv[base + m] = vals[m];
         d.sv[base + m] = svals[m];
@@ -352,7 +359,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     double* qs = sm + d.off_qs;
     double* pk = sm + d.off_pk;                                   // picks theta [b][6]
     double* red_v = sm + d.off_red;
-    int* red_i = reinterpret_cast<int*>(red_v + 256);
+    int* red_i = reinterpret_cast<int*>(red_v + BT);
     int* misc = reinterpret_cast<int*>(sm + d.off_misc);
     int* taken = misc;                                            // [C]
     int* rc = taken + C;                                          // [b][6] rounded cells
@@ -364,7 +371,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     const double inv_ls = 1.0 / d.ls;
 
     // ---- observations, standardised values
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += BT) {
         for (int a = 0; a < 6; ++a) X[6 * i + a] = (double)d.cells[(int64_t)(base + i) * 6 + a];
         yt[i] = d.yv[base + i];
     }
@@ -383,9 +390,9 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     __syncthreads();
     const double ym = red_v[0], ysd = red_v[1];
     __syncthreads();
-    for (int i = tid; i < n; i += 256) yt[i] = (yt[i] - ym) / ysd;
+    for (int i = tid; i < n; i += BT) yt[i] = (yt[i] - ym) / ysd;
     // ---- covariance (packed lower) and Cholesky, column by column
-    for (int e = tid; e < n * (n + 1) / 2; e += 256) {
+    for (int e = tid; e < n * (n + 1) / 2; e += BT) {
         int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
         while (tri(i + 1, 0) <= e) ++i;
         while (tri(i, 0) > e) --i;
@@ -401,7 +408,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         }
         __syncthreads();
         const double djj = L[tri(j, j)];
-        for (int i = j + 1 + tid; i < n; i += 256) {
+        for (int i = j + 1 + tid; i < n; i += BT) {
             double s = L[tri(i, j)];
             for (int p = 0; p < j; ++p) s -= L[tri(i, p)] * L[tri(j, p)];
             L[tri(i, j)] = s / djj;
@@ -440,7 +447,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     }
     // ---- candidates
     const int bi = uni(d.best[pair]);
-    for (int c = tid; c < C; c += 256) {
+    for (int c = tid; c < C; c += BT) {
         taken[c] = 0;
         for (int a = 0; a < 6; ++a) {
             const double up = (double)(axis_dim(A, B, a) - 1);
@@ -458,18 +465,44 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     }
     __syncthreads();
     // ---- posterior mean and q = L^-1 k per candidate (q kept in the scratch)
-    for (int c = tid; c < C; c += 256) {
+    // Rows are solved SOLVE_R at a time: each stored q_p is read once per block
+    // and applied to the block's rows; every row still subtracts its terms in
+    // ascending p, so the values are those of a plain row-by-row solve.
+    for (int c = tid; c < C; c += BT) {
         const double* x = th + 6 * c;
         double m = 0.0, ss = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const double ki = matern52(x, X + 6 * i, inv_ls);
-            m += ki * alpha[i];
-            double s = ki;
-            const double* Li = L + tri(i, 0);
-            for (int p = 0; p < i; ++p) s -= Li[p] * qcol[(int64_t)p * C + c];
-            const double qi = s / Li[i];
-            qcol[(int64_t)i * C + c] = qi;
-            ss += qi * qi;
+        for (int i0 = 0; i0 < n; i0 += SOLVE_R) {
+            const int nr = min(SOLVE_R, n - i0);
+            double sv[SOLVE_R], qb[SOLVE_R];
+#pragma unroll
+            for (int r = 0; r < SOLVE_R; ++r) {
+                sv[r] = 0.0;
+                qb[r] = 0.0;
+                if (r < nr) {
+                    const double ki = matern52(x, X + 6 * (i0 + r), inv_ls);
+                    m += ki * alpha[i0 + r];
+                    sv[r] = ki;
+                }
+            }
+            for (int p = 0; p < i0; ++p) {
+                const double qp = qcol[(int64_t)p * C + c];
+#pragma unroll
+                for (int r = 0; r < SOLVE_R; ++r)
+                    if (r < nr) sv[r] -= L[tri(i0 + r, p)] * qp;
+            }
+#pragma unroll
+            for (int r = 0; r < SOLVE_R; ++r) {
+                if (r < nr) {
+                    const double* Li = L + tri(i0 + r, 0);
+                    double v = sv[r];
+#pragma unroll
+                    for (int t = 0; t < r; ++t) v -= Li[i0 + t] * qb[t];
+                    const double qi = v / Li[i0 + r];
+                    qb[r] = qi;
+                    qcol[(int64_t)(i0 + r) * C + c] = qi;
+                    ss += qi * qi;
+                }
+            }
         }
         mu[c] = m;
         const double v = 1.0 - ss;
@@ -480,7 +513,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     for (int m = 0; m < b; ++m) {
         double bv = -1e300;
         int bidx = 0x7fffffff;
-        for (int c = tid; c < C; c += 256) {
+        for (int c = tid; c < C; c += BT) {
             if (taken[c]) continue;
             const double u = mu[c] + d.kappa * sqrt(s2[c]);
             if (u > bv || (u == bv && c < bidx)) {
@@ -490,7 +523,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         }
         const int cs = block_argmax(bv, bidx, red_v, red_i);
         const int rows = n + m;  // rows of q so far
-        for (int r = tid; r < rows; r += 256) qs[r] = qcol[(int64_t)r * C + cs];
+        for (int r = tid; r < rows; r += BT) qs[r] = qcol[(int64_t)r * C + cs];
         if (tid == 0) {
             taken[cs] = 1;
             for (int a = 0; a < 6; ++a) pk[6 * m + a] = th[6 * cs + a];
@@ -499,7 +532,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         const double dm = sqrt(s2[cs] + d.jitter > 1e-300 ? s2[cs] + d.jitter : 1e-300);
         const double* xs = th + 6 * cs;
         __syncthreads();
-        for (int c = tid; c < C; c += 256) {
+        for (int c = tid; c < C; c += BT) {
             double s = matern52(th + 6 * c, xs, inv_ls);
             for (int r = 0; r < rows; ++r) s -= qcol[(int64_t)r * C + c] * qs[r];
             const double u = s / dm;
@@ -511,7 +544,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     }
     // ---- rounding (Bernoulli of the fractional part) and dedupe
     const int slot0 = uni(d.slot[pair]);
-    for (int m = tid; m < b; m += 256) {
+    for (int m = tid; m < b; m += BT) {
         for (int a = 0; a < 6; ++a) {
             const double v = pk[6 * m + a];
             const double f = floor(v);
@@ -522,7 +555,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         }
     }
     __syncthreads();
-    for (int m = tid; m < b; m += 256) {
+    for (int m = tid; m < b; m += BT) {
         bool dupl = false;
         for (int i = 0; i < n && !dupl; ++i) {
             bool same = true;
@@ -553,7 +586,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     float* svals = reinterpret_cast<float*>(s2);
     eval_cells<KP1>(d, pair, newc, nn, vals, svals, reinterpret_cast<float*>(th));
     __syncthreads();
-    for (int m = tid; m < nn; m += 256) {
+    for (int m = tid; m < nn; m += BT) {
         for (int a = 0; a < 6; ++a) d.cells[(int64_t)(base + n + m) * 6 + a] = (int16_t)newc[6 * m + a];
         d.yv[base + n + m] = vals[m];
         d.sv[base + n + m] = svals[m];
@@ -573,7 +606,7 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
 }
 
 template <int KP1>
-__global__ __launch_bounds__(256) void bos_kernel(BosDev d) {
+__global__ __launch_bounds__(BT) void bos_kernel(BosDev d) {
     extern __shared__ __attribute__((aligned(16))) double sm[];
     const int it = uni(*d.iter);
     if (it >= d.n_iter) return;  // every pair is done
@@ -740,7 +773,7 @@ static const void* bos_kernel_for(int kp1) {
 }
 
 static void bos_launch_kernel(bos_state* st, hipStream_t s) {
-    const dim3 grid((unsigned)st->grid), block(256);
+    const dim3 grid((unsigned)st->grid), block(BT);
     switch (st->kp1) {
         case 0: bos_kernel<0><<<grid, block, st->lds_bytes, s>>>(st->d); break;
         case 4: bos_kernel<4><<<grid, block, st->lds_bytes, s>>>(st->d); break;
@@ -1001,13 +1034,13 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
     d.off_a = off; off += NT;
     d.off_qs = off; off += NT;
     d.off_pk = off; off += 6 * 64;
-    d.off_red = off; off += 256 + 128;
+    d.off_red = off; off += BT + BT / 2;
     d.off_mu = off; off += C;
     d.off_s2 = off; off += C;
     d.off_th = off;
     {
         // candidates theta, reused afterwards as the per-wave evaluation staging
-        const int stage_doubles = ksg ? (4 * (2 * ((A->M + 1) & ~1) + 2 * d.p2) + 1) / 2 : 0;
+        const int stage_doubles = ksg ? (NW * (2 * ((A->M + 1) & ~1) + 2 * d.p2) + 1) / 2 : 0;
         off += std::max(6 * C, stage_doubles);
     }
     d.off_misc = off;
@@ -1021,7 +1054,7 @@ int bos_create(corr_ctx* ctx, const corr_field* A, const corr_field* B, const co
         return fail(CORR_EUNSUPPORTED, "bos_create: configuration needs more than 160 KiB of LDS");
     }
     int per_cu = 1;
-    if ((rc = kernel_setup(bos_kernel_for(st->kp1), st->lds_bytes, 256, &per_cu))) {
+    if ((rc = kernel_setup(bos_kernel_for(st->kp1), st->lds_bytes, BT, &per_cu))) {
         bos_destroy(st);
         return rc;
     }
