@@ -1,11 +1,13 @@
 // Learned BOS proposal: a small MLP (forward, backward, AdamW) and the
 // region-pair inputs it reads (self-similarity hot spots and their cross
-// correlations). FP32 arithmetic on BF16-rounded weights; every sum runs
-// in a fixed order (no floating-point atomics), so runs are reproducible.
-//
-// The network is tiny (about 8e4 parameters); its layers are plain row-major
-// products, one thread per output with the input row staged in LDS, and the
-// weight gradient one thread per weight summing over the batch in order.
+// correlations). Weights are BF16-rounded copies of FP32 master weights;
+// every product of the forward and backward passes runs on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation), one wave per 32 x 32 output
+// block. FP32 operands (activations, gradients) enter as a BF16 hi part and
+// a BF16 lo part (x = hi + lo to about 2^-16 relative), and the products
+// hi.hi + hi.lo + lo.hi are accumulated, so the results carry FP32-level
+// accuracy; the BF16 weights are exact and need no lo part. No sum uses
+// floating-point atomics, so two runs are bitwise identical.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -30,21 +32,90 @@ __global__ void to_bf16_kernel(const float* __restrict__ p, __hip_bfloat16* __re
     if (i < n) q[i] = __float2bfloat16(p[i]);
 }
 
-// Z[b][n] = bias[n] + sum_k X[b][k] W[k][n]; A = silu(Z) when A != NULL.
-__global__ __launch_bounds__(256) void linear_fwd_kernel(const float* __restrict__ X, int K,
-                                                         const __hip_bfloat16* __restrict__ W,
-                                                         const __hip_bfloat16* __restrict__ bias, int N,
-                                                         float* __restrict__ Z, float* __restrict__ A) {
-    extern __shared__ float xs[];
-    const int b = blockIdx.x;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) xs[k] = X[(int64_t)b * K + k];
-    __syncthreads();
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        float z = bf(bias[n]);
-        for (int k = 0; k < K; ++k) z = fmaf(xs[k], bf(W[(int64_t)k * N + n]), z);
-        Z[(int64_t)b * N + n] = z;
-        if (A) A[(int64_t)b * N + n] = silu_f(z);
+typedef __bf16 mlp_b8 __attribute__((ext_vector_type(8)));
+typedef float mlp_f16 __attribute__((ext_vector_type(16)));
+
+// A matrix operand: element (i, j) at p[i * s0 + j * s1], FP32 or BF16.
+struct MatRef {
+    const void* p;
+    int bf16;
+    int64_t s0, s1;
+};
+
+__device__ __forceinline__ float mat_get(const MatRef& m, int64_t i, int64_t j) {
+    const int64_t o = i * m.s0 + j * m.s1;
+    return m.bf16 ? __bfloat162float(reinterpret_cast<const __hip_bfloat16*>(m.p)[o])
+                  : reinterpret_cast<const float*>(m.p)[o];
+}
+
+enum MlpEpilogue { EP_BIAS = 0, EP_DSILU = 1, EP_PLAIN = 2 };
+
+// C[i][j] = sum_k A(i, k) B(k, j) for i < R, j < N, one wave per 32 x 32
+// block (four per workgroup). Per K-step of 16, lane (l, h) (l = lane % 32,
+// h = lane / 32) holds A(row l, k = 8h .. 8h+7) and B(k = 8h .. 8h+7, col l);
+// accumulator register r of lane (l, h) is C(8 (r / 4) + 4 h + r % 4, l).
+// Epilogues: EP_BIAS: Z = C + bias[j] (BF16, may be NULL), Aout = silu(Z)
+// when Aout != NULL; EP_DSILU: C * silu'(Zp[i][j]); EP_PLAIN: C.
+__global__ __launch_bounds__(256) void mlp_mfma_gemm_kernel(MatRef A, MatRef B, int R, int N, int K, int ep,
+                                                            const __hip_bfloat16* __restrict__ bias,
+                                                            const float* __restrict__ Zp, float* __restrict__ C,
+                                                            float* __restrict__ Aout) {
+    const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+    const int nbn = (N + 31) / 32, nbm = (R + 31) / 32;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= nbm * nbn) return;  // wave-uniform; the kernel has no barriers
+    const int i0 = (w / nbn) * 32, j0 = (w % nbn) * 32;
+    const int row = i0 + l, col = j0 + l;
+    mlp_f16 acc = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        mlp_b8 ah, al, bh, bl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + 8 * h + e;
+            const float av = (row < R && k < K) ? mat_get(A, row, k) : 0.0f;
+            const float bv = (col < N && k < K) ? mat_get(B, k, col) : 0.0f;
+            ah[e] = (__bf16)av;
+            al[e] = (__bf16)(av - (float)ah[e]);
+            bh[e] = (__bf16)bv;
+            bl[e] = (__bf16)(bv - (float)bh[e]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        if (!A.bf16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+        if (!B.bf16) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (i >= R || col >= N) continue;
+        const int64_t o = (int64_t)i * N + col;
+        float v = acc[r];
+        if (ep == EP_BIAS) {
+            if (bias) v += bf(bias[col]);
+            C[o] = v;
+            if (Aout) Aout[o] = silu_f(v);
+        } else if (ep == EP_DSILU) {
+            C[o] = v * dsilu_f(Zp[o]);
+        } else {
+            C[o] = v;
+        }
+    }
+}
+
+// gb[n] = sum_b dZ[b][n], in batch order
+__global__ void col_sum_kernel(const float* __restrict__ dZ, int B, int N, float* __restrict__ gb) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float g = 0.0f;
+    for (int b = 0; b < B; ++b) g += dZ[(int64_t)b * N + n];
+    gb[n] = g;
+}
+
+static int mlp_gemm(MatRef A, MatRef B, int R, int N, int K, int ep, const __hip_bfloat16* bias, const float* Zp,
+                    float* C, float* Aout, hipStream_t s) {
+    const int blocks = ((R + 31) / 32) * ((N + 31) / 32);
+    mlp_mfma_gemm_kernel<<<dim3((unsigned)((blocks + 3) / 4)), 256, 0, s>>>(A, B, R, N, K, ep, bias, Zp, C, Aout);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
 }
 
 // dY = 2 w (Y - T) / (B n_out); per-row loss partial in a fixed order.
@@ -75,40 +146,6 @@ __global__ void loss_reduce_kernel(const float* __restrict__ part, int B, int n_
         __syncthreads();
     }
     if (threadIdx.x == 0) *loss = s[0] / ((float)B * (float)n_out);
-}
-
-// dZprev[b][k] = (sum_n dZ[b][n] W[k][n]) * silu'(Zprev[b][k])
-__global__ __launch_bounds__(256) void linear_bwd_data_kernel(const float* __restrict__ dZ, int N,
-                                                              const __hip_bfloat16* __restrict__ W, int K,
-                                                              const float* __restrict__ Zprev,
-                                                              float* __restrict__ dZprev) {
-    extern __shared__ float ds[];
-    const int b = blockIdx.x;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) ds[n] = dZ[(int64_t)b * N + n];
-    __syncthreads();
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        float a = 0.0f;
-        const __hip_bfloat16* wk = W + (int64_t)k * N;
-        for (int n = 0; n < N; ++n) a = fmaf(ds[n], bf(wk[n]), a);
-        dZprev[(int64_t)b * K + k] = a * dsilu_f(Zprev[(int64_t)b * K + k]);
-    }
-}
-
-// gW[k][n] = sum_b X[b][k] dZ[b][n] (blockIdx.y = k < K), gb[n] = sum_b dZ[b][n] (blockIdx.y = K)
-__global__ __launch_bounds__(256) void linear_bwd_weight_kernel(const float* __restrict__ X, const float* __restrict__ dZ,
-                                                                int B, int K, int N, float* __restrict__ gW,
-                                                                float* __restrict__ gb) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
-    if (n >= N) return;
-    float g = 0.0f;
-    if (k < K) {
-        for (int b = 0; b < B; ++b) g = fmaf(X[(int64_t)b * K + k], dZ[(int64_t)b * N + n], g);
-        gW[(int64_t)k * N + n] = g;
-    } else {
-        for (int b = 0; b < B; ++b) g += dZ[(int64_t)b * N + n];
-        gb[n] = g;
-    }
 }
 
 __global__ void adamw_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
@@ -375,14 +412,14 @@ static int mlp_forward_ws(prop_mlp* mm, const float* x, int B, hipStream_t s, fl
     *a2 = *z2 + (int64_t)B * H;
     *y = *a2 + (int64_t)B * H;
     to_bf16_kernel<<<dim3((unsigned)((mm->n + 255) / 256)), 256, 0, s>>>(mm->p, mm->pb, mm->n);
-    const int th = 256;
-    linear_fwd_kernel<<<dim3(B), th, sizeof(float) * mm->n_in, s>>>(x, mm->n_in, mm->pb + mm->oW1, mm->pb + mm->ob1, H,
-                                                                     *z1, *a1);
-    linear_fwd_kernel<<<dim3(B), th, sizeof(float) * H, s>>>(*a1, H, mm->pb + mm->oW2, mm->pb + mm->ob2, H, *z2, *a2);
-    linear_fwd_kernel<<<dim3(B), th, sizeof(float) * H, s>>>(*a2, H, mm->pb + mm->oW3, mm->pb + mm->ob3, mm->n_out, *y,
-                                                             nullptr);
     CORR_LAUNCH_CHECK();
-    return CORR_OK;
+    const int n_in = mm->n_in, no = mm->n_out;
+    // Z = X W + b with W stored [in][out]
+    const MatRef x_r{x, 0, n_in, 1}, a1_r{*a1, 0, H, 1}, a2_r{*a2, 0, H, 1};
+    const MatRef w1{mm->pb + mm->oW1, 1, H, 1}, w2{mm->pb + mm->oW2, 1, H, 1}, w3{mm->pb + mm->oW3, 1, no, 1};
+    if ((rc = mlp_gemm(x_r, w1, B, H, n_in, EP_BIAS, mm->pb + mm->ob1, nullptr, *z1, *a1, s))) return rc;
+    if ((rc = mlp_gemm(a1_r, w2, B, H, H, EP_BIAS, mm->pb + mm->ob2, nullptr, *z2, *a2, s))) return rc;
+    return mlp_gemm(a2_r, w3, B, no, H, EP_BIAS, mm->pb + mm->ob3, nullptr, *y, nullptr, s);
 }
 
 extern "C" {
@@ -505,17 +542,23 @@ int prop_mlp_train_step(prop_mlp* mm, const float* x, const float* target, const
     }
     out_grad_kernel<<<dim3((B + 255) / 256), 256, 0, s>>>(y, target, wdev, B, no, dY, part);
     loss_reduce_kernel<<<1, 256, 0, s>>>(part, B, no, mm->loss);
+    // per layer: gW = X^T dZ ([in][out], X as its transpose), gb = column sums
+    // of dZ, and dX = (dZ W^T) * silu'(Z_prev) (W [in][out] read transposed)
+    const int n_in = mm->n_in;
+    const MatRef dY_r{dY, 0, no, 1}, dz2_r{dz2, 0, H, 1}, dz1_r{dz1, 0, H, 1};
+    const MatRef a2_t{a2, 0, 1, H}, a1_t{a1, 0, 1, H}, x_t{x, 0, 1, n_in};
+    const MatRef w3_t{mm->pb + mm->oW3, 1, 1, no}, w2_t{mm->pb + mm->oW2, 1, 1, H};
     // layer 3
-    linear_bwd_weight_kernel<<<dim3((no + 255) / 256, H + 1), 256, 0, s>>>(a2, dY, B, H, no, mm->g + mm->oW3,
-                                                                          mm->g + mm->ob3);
-    linear_bwd_data_kernel<<<dim3(B), 256, sizeof(float) * no, s>>>(dY, no, mm->pb + mm->oW3, H, z2, dz2);
+    if ((rc = mlp_gemm(a2_t, dY_r, H, no, B, EP_PLAIN, nullptr, nullptr, mm->g + mm->oW3, nullptr, s))) return rc;
+    col_sum_kernel<<<dim3((no + 255) / 256), 256, 0, s>>>(dY, B, no, mm->g + mm->ob3);
+    if ((rc = mlp_gemm(dY_r, w3_t, B, H, no, EP_DSILU, nullptr, z2, dz2, nullptr, s))) return rc;
     // layer 2
-    linear_bwd_weight_kernel<<<dim3((H + 255) / 256, H + 1), 256, 0, s>>>(a1, dz2, B, H, H, mm->g + mm->oW2,
-                                                                         mm->g + mm->ob2);
-    linear_bwd_data_kernel<<<dim3(B), 256, sizeof(float) * H, s>>>(dz2, H, mm->pb + mm->oW2, H, z1, dz1);
+    if ((rc = mlp_gemm(a1_t, dz2_r, H, H, B, EP_PLAIN, nullptr, nullptr, mm->g + mm->oW2, nullptr, s))) return rc;
+    col_sum_kernel<<<dim3((H + 255) / 256), 256, 0, s>>>(dz2, B, H, mm->g + mm->ob2);
+    if ((rc = mlp_gemm(dz2_r, w2_t, B, H, H, EP_DSILU, nullptr, z1, dz1, nullptr, s))) return rc;
     // layer 1
-    linear_bwd_weight_kernel<<<dim3((H + 255) / 256, mm->n_in + 1), 256, 0, s>>>(x, dz1, B, mm->n_in, H,
-                                                                                mm->g + mm->oW1, mm->g + mm->ob1);
+    if ((rc = mlp_gemm(x_t, dz1_r, n_in, H, B, EP_PLAIN, nullptr, nullptr, mm->g + mm->oW1, nullptr, s))) return rc;
+    col_sum_kernel<<<dim3((H + 255) / 256), 256, 0, s>>>(dz1, B, H, mm->g + mm->ob1);
     mm->step += 1;
     const float bc1 = 1.0f - powf(0.9f, (float)mm->step), bc2 = 1.0f - powf(0.999f, (float)mm->step);
     adamw_kernel<<<dim3((unsigned)((mm->n + 255) / 256)), 256, 0, s>>>(mm->p, mm->g, mm->m, mm->v, mm->n, lr, wd, bc1,
@@ -553,7 +596,9 @@ int corr_proposal_inputs(corr_ctx* ctx, const corr_field* A, const corr_region* 
     const Box whole{0, 0, 0, A->nx, A->ny, A->nz, A->nx, A->ny};
     const int F = 4 * n_hot + 5;
     void *sb, *simb, *mb;
-    int rc = ws_get(ctx, WS_STATS_A, sizeof(float) * 4 * (size_t)P, s, &sb);
+    int rc = ctx_use_stream(ctx, s);
+    if (rc) return rc;
+    rc = ws_get(ctx, WS_STATS_A, sizeof(float) * 4 * (size_t)P, s, &sb);
     if (rc) return rc;
     Stats st = stats_view((float*)sb, P);
     if ((rc = launch_stats(*A, whole, true, st, s))) return rc;
