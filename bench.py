@@ -811,9 +811,10 @@ def large_legs(args, torch, synth, pc):
 
 def run_proposal(args, torch, synth, pc):
     """Learned BOS proposal at scale: records from ten context fields of the
-    352x256x20 generator (seeds 1000-1009, 88 regions, 3828 pairs each), the
-    58 -> 256 -> 256 -> 18 network trained on the GPU, then on two unseen
-    fields (seeds 2000, 2001) plain GPU BOS at 100 samples per pair against
+    352x256x20 generator (seeds 1000-1009, 88 regions, 3828 pairs each) and
+    the 4096 sub-brick pairs of a focus field (seed 1010, bricks split
+    4 x 4 x 4), the 58 -> 256 -> 256 -> 18 network trained on the GPU, then on
+    five unseen fields (seeds 9000-9004) plain GPU BOS at 100 samples per pair against
     GPU BOS seeded with the network's best candidate at 36 and 100 samples,
     each judged by the exhaustive FP16x3 maxima, planted and noise pairs apart.
     One step is one learned-proposal view at 36 samples per pair: inputs,
@@ -831,6 +832,22 @@ def run_proposal(args, torch, synth, pc):
         Ys.append(y)
         print(f"proposal: records of field {s}: {x.shape[0]}", file=sys.stderr, flush=True)
         del f
+    # sub-brick pairs of a focus field (seed 1010): each brick split 4 x 4 x 4
+    e = synth.make_cfg2(seed=1010)
+    f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
+    subs = []
+    for r in e.regions:
+        for z in range(4):
+            for y in range(4):
+                for x in range(4):
+                    subs.append(pc.region(r.x0 + x * (r.dx // 4), r.y0 + y * (r.dy // 4), r.z0 + z * (r.dz // 4),
+                                          r.dx // 4, r.dy // 4, r.dz // 4))
+    sub_pairs = np.array([(a, 64 + b) for a in range(64) for b in range(64)], np.int32)
+    x, y, _ = PR.make_records(ctx, f, subs, sub_pairs)
+    Xs.append(x)
+    Ys.append(y)
+    print(f"proposal: records of the focus field's sub-brick pairs: {x.shape[0]}", file=sys.stderr, flush=True)
+    del f
     t_rec = time.perf_counter() - t0
     X, Y = torch.cat(Xs), torch.cat(Ys)
     net = pc.PropMlp(ctx, X.shape[1], 256, PR.n_out(), seed=1)
@@ -842,7 +859,8 @@ def run_proposal(args, torch, synth, pc):
     print(f"proposal: trained on {X.shape[0]} records in {t_train:.1f} s", file=sys.stderr, flush=True)
     evals = {}
     view_ms = []
-    for s in (2000, 2001):
+    eval_seeds = (9000, 9001, 9002, 9003, 9004)
+    for s in eval_seeds:
         e = synth.make_cfg3(seed=s)
         f = pc.Field(torch.from_numpy(e.data).cuda(), e.nx, e.ny, e.nz)
         regs = [pc.region(*r.as_tuple()) for r in e.regions]
@@ -882,7 +900,7 @@ def run_proposal(args, torch, synth, pc):
     n36 = summary["learned36"]["evaluations"]
     extra = {"breakdown": {"training_records": int(X.shape[0]), "record_generation_s": t_rec,
                            "training_s": t_train, "epochs": epochs, "loss_first_last": [hist[0], hist[-1]],
-                           "unseen_fields": 2, "per_config": summary, "per_field": evals}}
+                           "unseen_fields": len(eval_seeds), "per_config": summary, "per_field": evals}}
     if not args.no_cpu_baseline:
         from oracle import mlp_ref
         n_in, H, n_o = X.shape[1], 256, PR.n_out()
@@ -904,8 +922,9 @@ def run_proposal(args, torch, synth, pc):
         extra["gpu_training_samples_per_s"] = X.shape[0] * epochs / t_train
     line = _line(args, n36 / (ms / 1e3), ms,
                  {"workload": "learned BOS proposal: trained on 10 context fields (352x256x20, 88 regions, M=100, "
-                              "seeds 1000-1009), judged on 2 unseen fields (seeds 2000-2001); step = one "
-                              "learned-proposal view at 36 samples per pair", "members": 100,
+                              "seeds 1000-1009) and the sub-brick pairs of a focus field (seed 1010), judged on 5 "
+                              "unseen fields (seeds 9000-9004); step = one learned-proposal view at 36 samples per "
+                              "pair", "members": 100,
                   "region_pairs": 3828, "network": "58-256-256-18 SiLU, BF16-rounded weights, FP32"}, **extra)
     line["unit"] = "evaluated point pairs/s"
     line["steps"], line["warmup"] = 2, 1

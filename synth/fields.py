@@ -191,15 +191,15 @@ def make_cfg1(copy_variant: bool = False) -> Ensemble:
     return e
 
 
-def make_cfg2() -> Ensemble:
+def make_cfg2(seed: int = 2) -> Ensemble:
     """80x32x20 grid, M=100, regions x in [0,32) and [48,80), 3 planted groups (r=4)."""
     ra, rb = Region(0, 0, 0, 32, 32, 20), Region(48, 0, 0, 32, 32, 20)
-    rng = np.random.Generator(np.random.PCG64(10_002))
+    rng = np.random.Generator(np.random.PCG64(10_000 + seed))
     ca = _place_centers(rng, ra, 3, 4, 10)
     cb = _place_centers(rng, rb, 3, 4, 10)
     groups = [{"rho": rho, "blobs": [(*ca[g], 4.0), (*cb[g], 4.0)]}
               for g, rho in enumerate((0.5, 0.8, 0.95))]
-    return make_field("focus-80x32x20-M100", 2, 100, 80, 32, 20, groups, [ra, rb])
+    return make_field("focus-80x32x20-M100", seed, 100, 80, 32, 20, groups, [ra, rb])
 
 
 def context_regions(ni: int, nj: int, dims=(32, 32, 20)):
