@@ -366,17 +366,23 @@ __global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n
             }
         } else {
             // A fragments double-buffered in registers: the next block's
-            // loads are in flight while the current block is multiplied
+            // loads are in flight while the current block is multiplied.
+            // The prefetch is unconditional (past the run's last block it
+            // re-reads that block): a conditional load would make the
+            // compiler's wait counting treat the current block's operands as
+            // the newest loads and wait for the prefetch before the first
+            // product, which serialises the two.
             uint4 av2[PARTS][WM][KV / 2];
             int64_t ab = ab0 + wave;
+            const int64_t ab_last = ab1 - 1;
             if (ab < ab1) sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
             while (ab < ab1) {
-                if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av2);
+                sk_load_a<PARTS, WM, KV>(g, min(ab + 4, ab_last) * 32 * WM, l32, half, rowb_g, av2);
                 sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av, acc,
                                                                  lane_best, lane_ab, lane_jg);
                 ab += 4;
                 if (ab >= ab1) break;
-                if (ab + 4 < ab1) sk_load_a<PARTS, WM, KV>(g, (ab + 4) * 32 * WM, l32, half, rowb_g, av);
+                sk_load_a<PARTS, WM, KV>(g, min(ab + 4, ab_last) * 32 * WM, l32, half, rowb_g, av);
                 sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av2, acc,
                                                                  lane_best, lane_ab, lane_jg);
                 ab += 4;
