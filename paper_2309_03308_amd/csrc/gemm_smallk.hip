@@ -81,16 +81,27 @@ __device__ __forceinline__ void sk_load_b(const char* smem, int jg, int l32, int
 // fences keep the reads where they are issued), so LDS latency is hidden
 // behind D steps of MFMAs instead of being waited for at every fragment.
 // Lookahead depth: as many K-steps (at most 4) as fit next to the A
-// fragments (doubled when prefetched), both accumulator sets (unless one
-// workgroup per CU leaves them the accumulation registers) and ~96 registers
-// of addressing and bookkeeping within 256 VGPRs; 0 when not even one step
-// fits (then each fragment is read just before its MFMAs).
-constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf, int occ) {
-    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + (occ == 1 ? 0 : 2 * wm * wng * 16) + 96;
+// fragments (doubled when prefetched), the accumulators (two sets when
+// double-buffered; none when one workgroup per CU leaves them the
+// accumulation registers) and ~96 registers of addressing and bookkeeping
+// within 256 VGPRs; 0 when not even one step fits (then each fragment is
+// read just before its MFMAs).
+constexpr int sk_depth(int parts, int wm, int wng, int ns, int pf, int occ, bool dbuf) {
+    const int fixed = parts * wm * ns * 4 * (pf ? 2 : 1) + (occ == 1 ? 0 : (dbuf ? 2 : 1) * wm * wng * 16) + 96;
     int d = (256 - fixed) / (parts * wng * 4) - 1;
     if (d > 4) d = 4;
     if (d > ns) d = ns;
     return d < 1 ? 0 : d;
+}
+// Interior blocks double-buffer the accumulators (the fold of one group
+// overlaps the next group's MFMAs) only where a lookahead still fits beside
+// them; otherwise the lookahead is kept and each group is folded after its
+// MFMAs, while the SIMD's other wave keeps the matrix pipe busy.
+constexpr bool sk_dbuf(int parts, int wm, int wng, int ns, int pf, int occ) {
+    return occ == 1 || sk_depth(parts, wm, wng, ns, pf, occ, true) >= 1;
+}
+constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf, int occ) {
+    return sk_depth(parts, wm, wng, ns, pf, occ, sk_dbuf(parts, wm, wng, ns, pf, occ));
 }
 
 // FOLD: while this group's MFMAs run, fold |r| of the previous group's
@@ -168,7 +179,8 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
                                          sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
     const int64_t row0 = ab * 32 * WM;
     const bool edge_rows = row0 + 32 * WM > g.na;
-    if (!edge_rows && !self && col0 + BN <= nb) {
+    constexpr bool DBUF = sk_dbuf(PARTS, WM, WNG, KV / 2, PF, OCC);
+    if (DBUF && !edge_rows && !self && col0 + BN <= nb) {
         // interior block: accumulators double-buffered, group q-1 folded
         // while group q is multiplied
         constexpr int NG = BN / 32 / WNG;
@@ -404,6 +416,7 @@ struct SkCfg {
 static const SkCfg kSkCfgs[] = {
     {2, 2, 256, 0, 2}, {1, 4, 256, 0, 2}, {2, 2, 128, 0, 2}, {1, 2, 128, 0, 2}, {1, 2, 128, 1, 2},
     {1, 4, 256, 1, 2}, {1, 2, 256, 1, 2}, {1, 2, 256, 0, 2}, {2, 4, 512, 0, 1}, {4, 2, 512, 0, 1},
+    {2, 1, 256, 0, 2}, {2, 1, 128, 0, 2},
 };
 constexpr int kNumSkCfgs = sizeof(kSkCfgs) / sizeof(kSkCfgs[0]);
 
@@ -472,6 +485,8 @@ static int launch_sk_p(const GemmArgs& g, int cfg, int nc, hipStream_t s, bool q
         case 7: return launch_sk_k<PREC, 1, 2, 256, 0>(g, nc, s, q);
         case 8: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 4, 512, 0, 1>(g, nc, s, q); break;
         case 9: if constexpr (!SPLIT) return launch_sk_k<PREC, 4, 2, 512, 0, 1>(g, nc, s, q); break;
+        case 10: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 1, 256, 0>(g, nc, s, q); break;
+        case 11: if constexpr (!SPLIT) return launch_sk_k<PREC, 2, 1, 128, 0>(g, nc, s, q); break;
     }
     return fail(CORR_EINVAL, "small-K contraction: tile configuration not available for this precision");
 }

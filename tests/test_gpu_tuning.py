@@ -44,11 +44,11 @@ def test_all_tile_configs_identical(env, tmp_path, prec):
     ctx, f, ra, rb = env["ctx"], env["f"], env["ra"], env["rb"]
     split = prec.endswith("x3")
     outs = {}
-    for cfg in range(10):
+    for cfg in range(12):
         # configurations with two row blocks per wave are not built for the
         # split modes (a configuration whose kernel would spill is replaced by
         # the default when the tuning record is loaded)
-        if split and cfg in (0, 2):
+        if split and cfg in (0, 2, 10, 11):
             continue
         _force(ctx, tmp_path, [dict(kind=0, K=112, prec=env["pc"].PREC[prec], na=20480, nb=20480, cfg=cfg, ms=0.0)])
         outs[cfg] = ctx.corr_region_max(f, ra, rb, "pearson", prec)
@@ -61,7 +61,7 @@ def test_autotune_and_roundtrip(env, tmp_path):
     ctx, f, ra, rb, pc = env["ctx"], env["f"], env["ra"], env["rb"], env["pc"]
     cfg, ms = ctx.corr_autotune(f, ra, rb, "f16", reps=3)
     _say(f"  autotune f16 -> cfg {cfg} {ms:.4f} ms")
-    assert 0 <= cfg < 10 and ms > 0
+    assert 0 <= cfg < 12 and ms > 0
     p = os.path.join(str(tmp_path), "saved.jsonl")
     ctx.corr_tune_save(p)
     recs = [json.loads(l) for l in open(p)]
