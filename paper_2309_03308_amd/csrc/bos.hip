@@ -52,6 +52,8 @@ constexpr int BT = 512;
 constexpr int NW = BT / 64;
 // Rows of the triangular solve handled per pass over the stored solve vectors.
 constexpr int SOLVE_R = 8;
+// values of a q column kept in flight by the Kriging-believer update
+constexpr int BELIEF_R = 16;
 
 __device__ inline double ph_gauss(uint64_t seed, uint64_t pair, uint64_t stream, uint64_t index, uint64_t axis) {
     uint64_t o[4];
@@ -252,24 +254,39 @@ __device__ inline int axis_dim(const Box& A, const Box& B, int a) {
 
 // Block-wide argmax of (value, -index) over LDS scratch; returns the index.
 __device__ int block_argmax(double v, int idx, double* red_v, int* red_i) {
-    const int tid = threadIdx.x;
-    red_v[tid] = v;
-    red_i[tid] = idx;
-    __syncthreads();
-    for (int s = BT / 2; s >= 1; s >>= 1) {
-        if (tid < s) {
-            const double ov = red_v[tid + s];
-            const int oi = red_i[tid + s];
-            if (ov > red_v[tid] || (ov == red_v[tid] && oi < red_i[tid])) {
-                red_v[tid] = ov;
-                red_i[tid] = oi;
-            }
+    // (value, index) pairs are ordered by value, then by smaller index: the
+    // winner is unique, so the reduction order does not change it. A wave
+    // butterfly leaves every lane with its wave's winner, one lane per wave
+    // publishes it and, after one barrier, every thread reduces the NW
+    // entries itself. Two calls must be separated by a barrier (the slots
+    // are rewritten by the next call).
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
         }
-        __syncthreads();
     }
-    const int r = uni(red_i[0]);
+    if (lane == 0) {
+        red_v[wave] = v;
+        red_i[wave] = idx;
+    }
     __syncthreads();
-    return r;
+    double bv = red_v[0];
+    int bi = red_i[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        const double ov = red_v[w];
+        const int oi = red_i[w];
+        if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    return uni(bi);
 }
 
 template <int KP1>
@@ -391,7 +408,12 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
     const double ym = red_v[0], ysd = red_v[1];
     __syncthreads();
     for (int i = tid; i < n; i += BT) yt[i] = (yt[i] - ym) / ysd;
-    // ---- covariance (packed lower) and Cholesky, column by column
+    // ---- covariance (packed lower) and Cholesky, right-looking: once column
+    // p is final every trailing element (i, j), p < j <= i, subtracts
+    // L_ip L_jp in parallel. Each element subtracts its terms in ascending p
+    // and is then divided by (or, on the diagonal, square-rooted from) the
+    // same values as in a column-by-column factorisation, so the factor is
+    // the same bit for bit; the dependent chain is n steps instead of ~n^2.
     for (int e = tid; e < n * (n + 1) / 2; e += BT) {
         int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
         while (tri(i + 1, 0) <= e) ++i;
@@ -400,19 +422,24 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         L[e] = matern52(X + 6 * i, X + 6 * j, inv_ls) + (i == j ? d.jitter : 0.0);
     }
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            double s = L[tri(j, j)];
-            for (int p = 0; p < j; ++p) s -= L[tri(j, p)] * L[tri(j, p)];
-            L[tri(j, j)] = sqrt(s > 1e-300 ? s : 1e-300);
-        }
+    for (int p = 0; p < n; ++p) {
+        const double app = L[tri(p, p)];
+        const double dpp = sqrt(app > 1e-300 ? app : 1e-300);
+        for (int i = p + 1 + tid; i < n; i += BT) L[tri(i, p)] = L[tri(i, p)] / dpp;
         __syncthreads();
-        const double djj = L[tri(j, j)];
-        for (int i = j + 1 + tid; i < n; i += BT) {
-            double s = L[tri(i, j)];
-            for (int p = 0; p < j; ++p) s -= L[tri(i, p)] * L[tri(j, p)];
-            L[tri(i, j)] = s / djj;
+        // trailing triangle over an m x m square (e -> row e / m, column
+        // e % m; exact in FP32 for m <= 127, as n_total <= 128)
+        const int m = n - p - 1;
+        const float inv_m = 1.0f / (float)(m > 0 ? m : 1);
+        for (int e = tid; e < m * m; e += BT) {
+            const int ii = (int)(((float)e + 0.5f) * inv_m);
+            const int jj = e - ii * m;
+            if (jj <= ii) {
+                const int i = p + 1 + ii, j = p + 1 + jj;
+                L[tri(i, j)] -= L[tri(i, p)] * L[tri(j, p)];
+            }
         }
+        if (tid == 0) L[tri(p, p)] = dpp;
         __syncthreads();
     }
     // ---- alpha = K^-1 yt: two triangular solves by wave 0 (lane owns rows l, l+64)
@@ -473,7 +500,11 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         double m = 0.0, ss = 0.0;
         for (int i0 = 0; i0 < n; i0 += SOLVE_R) {
             const int nr = min(SOLVE_R, n - i0);
-            double sv[SOLVE_R], qb[SOLVE_R];
+            double sv[SOLVE_R], qb[SOLVE_R], qv[SOLVE_R], qn[SOLVE_R];
+            // the first chunk of stored values is in flight during the
+            // covariances below (row 0.. of q; re-read, unused, when i0 == 0)
+#pragma unroll
+            for (int u = 0; u < SOLVE_R; ++u) qv[u] = qcol[(int64_t)min(u, max(i0 - 1, 0)) * C + c];
 #pragma unroll
             for (int r = 0; r < SOLVE_R; ++r) {
                 sv[r] = 0.0;
@@ -484,11 +515,30 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
                     sv[r] = ki;
                 }
             }
-            for (int p = 0; p < i0; ++p) {
-                const double qp = qcol[(int64_t)p * C + c];
+            // i0 is a multiple of SOLVE_R: the stored values are read
+            // SOLVE_R at a time, the next chunk's loads in flight while the
+            // current one is applied (the last chunk is re-read past the end
+            // so that every load is unconditional)
+            if (i0 > 0) {
+                for (int p0 = 0; p0 < i0; p0 += SOLVE_R) {
+                    const int pn = min(p0 + SOLVE_R, i0 - SOLVE_R);
 #pragma unroll
-                for (int r = 0; r < SOLVE_R; ++r)
-                    if (r < nr) sv[r] -= L[tri(i0 + r, p)] * qp;
+                    for (int u = 0; u < SOLVE_R; ++u) qn[u] = qcol[(int64_t)(pn + u) * C + c];
+                    if (nr == SOLVE_R) {  // every block but the last: no row tests
+#pragma unroll
+                        for (int u = 0; u < SOLVE_R; ++u)
+#pragma unroll
+                            for (int r = 0; r < SOLVE_R; ++r) sv[r] -= L[tri(i0 + r, p0 + u)] * qv[u];
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < SOLVE_R; ++u)
+#pragma unroll
+                            for (int r = 0; r < SOLVE_R; ++r)
+                                if (r < nr) sv[r] -= L[tri(i0 + r, p0 + u)] * qv[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < SOLVE_R; ++u) qv[u] = qn[u];
+                }
             }
 #pragma unroll
             for (int r = 0; r < SOLVE_R; ++r) {
@@ -523,18 +573,40 @@ __device__ void bos_batch_pair(const BosDev& d, int pair, int t, double* sm) {
         }
         const int cs = block_argmax(bv, bidx, red_v, red_i);
         const int rows = n + m;  // rows of q so far
+        // s2[cs] is read before the barrier: after it, thread cs updates it
+        const double dm = sqrt(s2[cs] + d.jitter > 1e-300 ? s2[cs] + d.jitter : 1e-300);
+        const double* xs = th + 6 * cs;
         for (int r = tid; r < rows; r += BT) qs[r] = qcol[(int64_t)r * C + cs];
         if (tid == 0) {
             taken[cs] = 1;
             for (int a = 0; a < 6; ++a) pk[6 * m + a] = th[6 * cs + a];
         }
         __syncthreads();
-        const double dm = sqrt(s2[cs] + d.jitter > 1e-300 ? s2[cs] + d.jitter : 1e-300);
-        const double* xs = th + 6 * cs;
-        __syncthreads();
         for (int c = tid; c < C; c += BT) {
+            // The column of q is streamed BELIEF_R values at a time: the first
+            // chunk is in flight during the covariance, each next chunk during
+            // the current one's terms (loads past `rows` re-read row rows - 1
+            // and are not used). Terms are subtracted in ascending r, as in a
+            // plain loop.
+            const double* qc = qcol + c;
+            double qv[BELIEF_R], qn[BELIEF_R];
+#pragma unroll
+            for (int u = 0; u < BELIEF_R; ++u) qv[u] = qc[(int64_t)min(u, rows - 1) * C];
             double s = matern52(th + 6 * c, xs, inv_ls);
-            for (int r = 0; r < rows; ++r) s -= qcol[(int64_t)r * C + c] * qs[r];
+            for (int r = 0; r < rows; r += BELIEF_R) {
+#pragma unroll
+                for (int u = 0; u < BELIEF_R; ++u) qn[u] = qc[(int64_t)min(r + BELIEF_R + u, rows - 1) * C];
+                if (r + BELIEF_R <= rows) {
+#pragma unroll
+                    for (int u = 0; u < BELIEF_R; ++u) s -= qv[u] * qs[r + u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < BELIEF_R; ++u)
+                        if (r + u < rows) s -= qv[u] * qs[r + u];
+                }
+#pragma unroll
+                for (int u = 0; u < BELIEF_R; ++u) qv[u] = qn[u];
+            }
             const double u = s / dm;
             qcol[(int64_t)rows * C + c] = u;
             const double v = s2[c] - u * u;
