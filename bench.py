@@ -41,7 +41,8 @@ sys.path.insert(0, ROOT)
 N_PEARSON = 20480 * 20480
 N_KSG = 1_000_000
 M = 100
-VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock
+# published FP32 vector rate (157.3 TFLOP/s) in FMA lane-ops/s: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz
+VALU_LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
 MFMA_F16_PEAK = 2.5e15
 LDS_BYTES_PER_S = 256 * 128 * 2.4e9  # CUs x LDS bytes per clock x clock
 HBM_PEAK = 8.0e12
@@ -172,7 +173,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="f16", choices=["f32", "f16", "bf16", "f16x3", "bf16x3"])
     ap.add_argument("--workload", default="focus", choices=["focus", "context", "large", "onetoall", "meantree", "meantree-dev", "samplers",
-                             "proposal"],
+                             "proposal", "peaks"],
                     help="focus: the headline focus-view step (default); context: batched BOS over the 3828 "
                          "region pairs of a 352x256x20 field; large: M=1000 FP16 ensemble rates; onetoall: one "
                          "reference point against every point of a 250x352x20 field (M=100) and of the "
@@ -180,8 +181,8 @@ def main():
                          "640x704x64 field; meantree-dev: deviation of brick maxima on those levels over the 3828 "
                          "brick pairs of the 352x256x20 field; samplers: convergence of uniform / Halton / plastic "
                          "sampled maxima over those pairs and on 6-D Gaussian test objectives; proposal: the "
-                         "learned BOS proposal trained on ten 88-region context fields and judged on two unseen "
-                         "ones against plain BOS and exhaustive maxima")
+                         "learned BOS proposal trained on ten 88-region context fields and judged on five unseen "
+                         "ones against plain BOS and exhaustive maxima; peaks: the device's measured peaks")
     ap.add_argument("--measure", default="pearson", choices=["pearson", "ksg"], help="BOS objective (context)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true",
@@ -214,6 +215,8 @@ def main():
         return run_samplers(args, torch, synth, pc)
     if args.workload == "proposal":
         return run_proposal(args, torch, synth, pc)
+    if args.workload == "peaks":
+        return run_peaks(args, torch, synth, pc)
     return run_focus(args, torch, synth, pc)
 
 
@@ -229,6 +232,60 @@ def _line(args, value, ms, config, **extra):
 
 
 FP64_VALU_PEAK = 78.6e12  # MI355X FP64 vector, flop/s
+
+
+def measure_peaks(torch, pc, reps=3):
+    """On-device peaks from the library's probes (include/corr_peaks.h): LDS read
+    bandwidth, dense FP16 MFMA, FP32 / FP64 vector FMA and HBM read bandwidth.
+    Each figure is the best of `reps` launches timed with HIP events on the
+    stream they run on (one untimed launch first); work / time."""
+    s = torch.cuda.current_stream()
+    nb = 2048                       # 8 workgroups of 256 threads per CU
+    o32 = torch.empty(nb * 256, dtype=torch.float32, device="cuda")
+    o64 = torch.empty(nb * 256, dtype=torch.float64, device="cuda")
+    oi = torch.empty(nb * 256, dtype=torch.int32, device="cuda")
+    hbm = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+
+    def best_s(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1) / 1e3)
+        return min(t)
+
+    it_lds, it_mfma, it_f32, it_f64 = 3000, 10000, 20000, 40000
+    lds = nb * 256 * it_lds * 128 / best_s(lambda: pc.corr_peak_lds(nb, it_lds, oi))
+    mfma = nb * 4 * it_mfma * 4 * 32768 / best_s(lambda: pc.corr_peak_mfma_f16(nb, it_mfma, o32))
+    f32 = nb * 256 * it_f32 * 16 * 2 / best_s(lambda: pc.corr_peak_valu_f32(nb, it_f32, o32))
+    med3 = nb * 256 * it_f32 * 16 / best_s(lambda: pc.corr_peak_valu_med3(nb, it_f32, o32))
+    f64 = nb * 256 * it_f64 * 8 * 2 / best_s(lambda: pc.corr_peak_valu_f64(nb, it_f64, o64))
+    hb = hbm.numel() / best_s(lambda: pc.corr_peak_hbm_read(hbm, nb, oi))
+    del hbm
+    return {"lds_read_TBps": lds / 1e12, "mfma_f16_TFLOPs": mfma / 1e12, "valu_f32_fma_TFLOPs": f32 / 1e12,
+            "valu_lane_ops_Tops": f32 / 2 / 1e12, "valu_med3_lane_ops_Tops": med3 / 1e12,
+            "valu_f64_fma_TFLOPs": f64 / 1e12, "hbm_read_GBps": hb / 1e9,
+            "vendor": {"lds_read_TBps": 78.6, "mfma_f16_TFLOPs": 2500.0, "valu_lane_ops_Tops": 78.6432,
+                       "valu_f64_fma_TFLOPs": 78.6, "hbm_read_GBps": 8000.0},
+            "method": "corr_peak_* probes, 2048 workgroups of 256 threads, best of 3 launches (HIP events); "
+                      "VALU without packed FP32 (lane-ops = FMA flops / 2)"}
+
+
+def with_measured_peak(roof, peaks):
+    """Add the measured peak of the roofline's bound (and the fraction of it) beside the vendor one."""
+    if not roof or not peaks:
+        return roof
+    key = {("mfma", "TFLOP/s"): "mfma_f16_TFLOPs", ("alu", "Tops/s"): "valu_lane_ops_Tops",
+           ("alu", "TFLOP/s"): "valu_f64_fma_TFLOPs"}.get((roof.get("bound"), roof.get("unit")))
+    pm = peaks["hbm_read_GBps"] if roof.get("bound") == "hbm" else (peaks[key] if key else None)
+    if pm and roof.get("achieved") is not None:
+        roof["peak_measured"] = pm
+        roof["frac_of_measured"] = roof["achieved"] / pm
+    return roof
 
 
 def bos_flops(schedule, n_init, C):
@@ -1036,9 +1093,11 @@ def run_focus(args, torch, synth, pc):
             "pearson_max": res["pearson"]["value"],
             "ksg_max": res["ksg"]["value"],
             "autotuned": {"contraction_cfg": tuned_cfg, "contraction_ms": tuned_ms, "ksg_workgroups_per_cu": tuned_pw},
-            # what binds KSG: VALU issue (counters) versus the LDS stream of
-            # neighbour samples (8 B per distance) against 256 CU x 128 B/clk x 2.4 GHz
-            "ksg_valu_busy_counters": measured_value("valu_busy"),
+            # what binds KSG: the issue of its VALU instructions (counters: wave
+            # instructions per SIMD cycle; the insertion network's v_med3_f32 issue
+            # once per 4 cycles, add/sub/max/FMA about every 2.5) versus the LDS
+            # stream of neighbour samples (8 B per distance) against 256 CU x 128 B/clk x 2.4 GHz
+            "ksg_valu_instructions_per_simd_cycle": measured_value("valu_insts_per_simd_cycle"),
             "ksg_lds_frac": N_KSG * M * (M - 1) * 8.0 / (ksg_ms / 1e3) / LDS_BYTES_PER_S,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
@@ -1085,6 +1144,22 @@ def run_focus(args, torch, synth, pc):
         per["bos_context_view_pearson"], _, _ = context_view(torch, synth, pc, "pearson", 3, 1,
                                                               0 if args.no_cpu_baseline else 30)
     line["per_measure"] = per
+    # the rooflines against the device's measured peaks, beside the vendor ones (untimed)
+    peaks = measure_peaks(torch, pc)
+    line["measured_peaks"] = peaks
+    with_measured_peak(line["roofline"], peaks)
+    for v in per.values():
+        if isinstance(v.get("roofline"), dict) and v["roofline"] is not line["roofline"]:
+            with_measured_peak(v["roofline"], peaks)
+    print(json.dumps(line), flush=True)
+
+
+def run_peaks(args, torch, synth, pc):
+    """The device's measured peaks alone (the default line carries them too)."""
+    peaks = measure_peaks(torch, pc)
+    line = _line(args, peaks["mfma_f16_TFLOPs"], 0.0, {"workload": "peak probes (LDS, FP16 MFMA, FP32/FP64 VALU, "
+                                                                   "HBM read) on the device"}, measured_peaks=peaks)
+    line["metric"], line["unit"], line["steps"], line["warmup"] = "measured dense FP16 MFMA peak", "TFLOP/s", 1, 0
     print(json.dumps(line), flush=True)
 
 

@@ -540,5 +540,42 @@ def corr_proposal_inputs(ctx: Context, A: Field, regions, region_pairs, n_hot: i
     return x, hot
 
 
+def _peak(name, n_blocks, iters, out, stream):
+    _lib.check(getattr(_lib.load(), name)(int(n_blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
+                                         _stream_ptr(stream)))
+
+
+def corr_peak_lds(n_blocks: int, iters: int, out, stream=None):
+    """LDS read probe (include/corr_peaks.h); out: device uint32/int32, >= n_blocks * 256."""
+    _peak("corr_peak_lds", n_blocks, iters, out, stream)
+
+
+def corr_peak_mfma_f16(n_blocks: int, iters: int, out, stream=None):
+    """FP16 MFMA probe; out: device float32, >= n_blocks * 256."""
+    _peak("corr_peak_mfma_f16", n_blocks, iters, out, stream)
+
+
+def corr_peak_valu_f32(n_blocks: int, iters: int, out, stream=None):
+    """FP32 vector FMA probe; out: device float32, >= n_blocks * 256."""
+    _peak("corr_peak_valu_f32", n_blocks, iters, out, stream)
+
+
+def corr_peak_valu_med3(n_blocks: int, iters: int, out, stream=None):
+    """FP32 median (v_med3_f32) issue probe; out: device float32, >= n_blocks * 256."""
+    _peak("corr_peak_valu_med3", n_blocks, iters, out, stream)
+
+
+def corr_peak_valu_f64(n_blocks: int, iters: int, out, stream=None):
+    """FP64 vector FMA probe; out: device float64, >= n_blocks * 256."""
+    _peak("corr_peak_valu_f64", n_blocks, iters, out, stream)
+
+
+def corr_peak_hbm_read(buf, n_blocks: int, out, stream=None):
+    """HBM read probe over the whole device tensor buf (16-byte aligned); out: device uint32, >= n_blocks * 256."""
+    nbytes = buf.numel() * buf.element_size()
+    _lib.check(_lib.load().corr_peak_hbm_read(ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(nbytes), int(n_blocks),
+                                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+
+
 def version() -> str:
     return _lib.load().corr_version().decode()

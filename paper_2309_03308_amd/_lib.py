@@ -117,6 +117,12 @@ SIGNATURES = {
     "prop_mlp_destroy": (None, [_P]),
     "corr_proposal_inputs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I32, _P, _I32, _I32,
                                   _I32, _I32, _P, _P, _P]),
+    "corr_peak_lds": (_I, [_I, _I, _P, _P]),
+    "corr_peak_mfma_f16": (_I, [_I, _I, _P, _P]),
+    "corr_peak_valu_f32": (_I, [_I, _I, _P, _P]),
+    "corr_peak_valu_med3": (_I, [_I, _I, _P, _P]),
+    "corr_peak_valu_f64": (_I, [_I, _I, _P, _P]),
+    "corr_peak_hbm_read": (_I, [_P, ctypes.c_size_t, _I, _P, _P]),
 }
 
 

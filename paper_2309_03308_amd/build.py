@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libcorr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "standardize.hip", "pairs.hip", "ksg.hip", "gemm.hip", "gemm_smallk.hip", "bos.hip", "mlp.hip", "aggregate.hip", "sampling.hip"]
+SOURCES = ["api.hip", "standardize.hip", "pairs.hip", "ksg.hip", "gemm.hip", "gemm_smallk.hip", "bos.hip", "mlp.hip", "aggregate.hip", "sampling.hip", "peaks.hip"]
 
 # The contraction kernels only see finite standardised values (|r| <= 1), so
 # they run with IEEE mode off: max/min need no NaN quieting of MFMA results.

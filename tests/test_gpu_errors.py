@@ -2,7 +2,9 @@
 precisions the library does not handle, CORR_ENOMEM when a call's
 workspaces would pass the context's cap (returned before any work is
 enqueued, the context usable afterwards), and calls that switch streams on
-one context (ordered by the library, same results)."""
+one context (ordered by the library, same results). Also the peak probes
+(corr_peaks.h): each runs and writes its words, bad arguments give
+CORR_EINVAL."""
 import numpy as np
 import pytest
 
@@ -85,3 +87,27 @@ def test_stream_switch_is_ordered(env):
     torch.cuda.synchronize()
     assert torch.equal(r1, r0) and torch.equal(mi2, mi0)
     assert np.all(np.isfinite(r1.cpu().numpy()))
+
+
+def test_peak_probes(env):
+    torch, pc, lib = env["torch"], env["pc"], env["lib"]
+    nb = 64
+    o32 = torch.full((nb * 256,), float("nan"), dtype=torch.float32, device="cuda")
+    o64 = torch.full((nb * 256,), float("nan"), dtype=torch.float64, device="cuda")
+    oi = torch.zeros(nb * 256, dtype=torch.int32, device="cuda")
+    pc.corr_peak_mfma_f16(nb, 10, o32)
+    torch.cuda.synchronize()
+    assert torch.isfinite(o32).all()
+    o32.fill_(float("nan"))
+    pc.corr_peak_valu_f32(nb, 10, o32)
+    pc.corr_peak_valu_f64(nb, 10, o64)
+    pc.corr_peak_valu_med3(nb, 10, o32)
+    torch.cuda.synchronize()
+    assert torch.isfinite(o32).all() and torch.isfinite(o64).all()
+    pc.corr_peak_lds(nb, 4, oi)
+    buf = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    pc.corr_peak_hbm_read(buf, nb, oi)
+    torch.cuda.synchronize()
+    assert _status(lambda: pc.corr_peak_lds(0, 4, oi), pc) == lib.CORR_EINVAL
+    assert _status(lambda: pc.corr_peak_mfma_f16(nb, 0, o32), pc) == lib.CORR_EINVAL
+    assert _status(lambda: pc.corr_peak_hbm_read(buf[1:5], nb, oi), pc) == lib.CORR_EINVAL  # misaligned
