@@ -540,14 +540,24 @@ def corr_proposal_inputs(ctx: Context, A: Field, regions, region_pairs, n_hot: i
     return x, hot
 
 
-def _peak(name, n_blocks, iters, out, stream):
+def _peak_out(out, n_blocks, dtypes):
+    """The probes write one word per thread: out must be a device tensor of n_blocks * 256 words."""
+    torch = _torch()
+    if not out.is_cuda or out.dtype not in [getattr(torch, d) for d in dtypes] or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous device tensor of dtype {' or '.join(dtypes)}")
+    if out.numel() < int(n_blocks) * 256:
+        raise ValueError(f"out must hold at least n_blocks * 256 = {int(n_blocks) * 256} elements")
+
+
+def _peak(name, n_blocks, iters, out, stream, dtypes=("float32",)):
+    _peak_out(out, n_blocks, dtypes)
     _lib.check(getattr(_lib.load(), name)(int(n_blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
                                          _stream_ptr(stream)))
 
 
 def corr_peak_lds(n_blocks: int, iters: int, out, stream=None):
     """LDS read probe (include/corr_peaks.h); out: device uint32/int32, >= n_blocks * 256."""
-    _peak("corr_peak_lds", n_blocks, iters, out, stream)
+    _peak("corr_peak_lds", n_blocks, iters, out, stream, ("int32", "uint32"))
 
 
 def corr_peak_mfma_f16(n_blocks: int, iters: int, out, stream=None):
@@ -567,11 +577,14 @@ def corr_peak_valu_med3(n_blocks: int, iters: int, out, stream=None):
 
 def corr_peak_valu_f64(n_blocks: int, iters: int, out, stream=None):
     """FP64 vector FMA probe; out: device float64, >= n_blocks * 256."""
-    _peak("corr_peak_valu_f64", n_blocks, iters, out, stream)
+    _peak("corr_peak_valu_f64", n_blocks, iters, out, stream, ("float64",))
 
 
 def corr_peak_hbm_read(buf, n_blocks: int, out, stream=None):
     """HBM read probe over the whole device tensor buf (16-byte aligned); out: device uint32, >= n_blocks * 256."""
+    _peak_out(out, n_blocks, ("int32", "uint32"))
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
     nbytes = buf.numel() * buf.element_size()
     _lib.check(_lib.load().corr_peak_hbm_read(ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(nbytes), int(n_blocks),
                                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))

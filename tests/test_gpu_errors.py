@@ -111,3 +111,5 @@ def test_peak_probes(env):
     assert _status(lambda: pc.corr_peak_lds(0, 4, oi), pc) == lib.CORR_EINVAL
     assert _status(lambda: pc.corr_peak_mfma_f16(nb, 0, o32), pc) == lib.CORR_EINVAL
     assert _status(lambda: pc.corr_peak_hbm_read(buf[1:5], nb, oi), pc) == lib.CORR_EINVAL  # misaligned
+    with pytest.raises(ValueError):  # fewer than n_blocks * 256 words: refused by the binding
+        pc.corr_peak_valu_f32(nb + 1, 10, o32)
