@@ -103,21 +103,55 @@ constexpr bool sk_dbuf(int parts, int wm, int wng, int ns, int pf, int occ) {
 constexpr int sk_lookahead(int parts, int wm, int wng, int ns, int pf, int occ) {
     return sk_depth(parts, wm, wng, ns, pf, occ, sk_dbuf(parts, wm, wng, ns, pf, occ));
 }
+// Largest batch of at most 8 vectors that divides a thread's share (more
+// would hold too many registers at a run's start).
+constexpr int sk_batch(int per) {
+    for (int c = 8; c > 1; --c)
+        if (per % c == 0) return c;
+    return 1;
+}
+
+// The lookahead crosses group boundaries: during a group's last D K-steps
+// the first D steps of the next group (the next block's first group after a
+// block's last one: the B tile stays in LDS for the whole run) are read into
+// the slots of steps already consumed, so a group's first products never
+// wait for LDS. Needs 0 < D < NS (a slot must be free before its reload).
+constexpr bool sk_xgroup(int parts, int wm, int wng, int ns, int pf, int occ) {
+    return sk_lookahead(parts, wm, wng, ns, pf, occ) > 0 && sk_lookahead(parts, wm, wng, ns, pf, occ) < ns;
+}
+
+// First D steps of group jg, when the lookahead crosses groups (the start of
+// a chain of groups: a run's first block, or a lone recomputed group).
+template <int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC>
+__device__ __forceinline__ void sk_prologue(const char* smem, int jg, int l32, int half,
+                                            uint4 (&bv)[PARTS][WNG][KV / 2]) {
+    constexpr int NS = KV / 2;
+    constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF, OCC);
+    if constexpr (sk_xgroup(PARTS, WM, WNG, NS, PF, OCC)) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s, bv);
+    }
+}
 
 // FOLD: while this group's MFMAs run, fold |r| of the previous group's
-// accumulators (prev) into mprev, a slice per K-step, so the VALU work
-// overlaps the matrix pipe instead of following it.
+// accumulators (prev) into mprev, a slice per K-step from the second one on
+// (the previous group's last products are still in the pipe at the first),
+// so the VALU work overlaps the matrix pipe instead of following it.
+// bv: on entry (cross-group lookahead) it holds steps 0..D-1 of group jg; on
+// exit, steps 0..D-1 of group jg_next.
 template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC, bool FOLD = false>
-__device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int half,
+__device__ __forceinline__ void sk_group(const char* smem, int jg, int jg_next, int l32, int half,
                                          const uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG],
-                                         const sk_f16 (&prev)[WM][WNG], float& mprev) {
+                                         const sk_f16 (&prev)[WM][WNG], float& mprev, uint4 (&bv)[PARTS][WNG][KV / 2]) {
     using T = SkT<PREC>;
     constexpr int NS = KV / 2;
     constexpr int NPAIR = WM * WNG * 8;  // element pairs of one group per lane
     constexpr int D = sk_lookahead(PARTS, WM, WNG, NS, PF, OCC);
-    uint4 bv[PARTS][WNG][NS];
+    constexpr bool XG = sk_xgroup(PARTS, WM, WNG, NS, PF, OCC);
+    if constexpr (!XG) {
 #pragma unroll
-    for (int s = 0; s < D; ++s) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s, bv);
+        for (int s = 0; s < D; ++s) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s, bv);
+    }
     if constexpr (D > 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -125,7 +159,10 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
         for (int j = 0; j < WNG; ++j) acc[i][j] = sk_f16{};
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        if (s + D < NS) sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s + D, bv);
+        if (s + D < NS)
+            sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg, l32, half, s + D, bv);
+        else if constexpr (XG)
+            sk_load_b<PARTS, WNG, NS, BN, ROWB>(smem, jg_next, l32, half, s + D - NS, bv);
         if constexpr (D > 0) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < WNG; ++j) {
@@ -162,8 +199,11 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
             }
         }
         if constexpr (FOLD) {
+            // slices over steps 1..NS-1 (all at step 0 when NS == 1)
+            constexpr int NSL = NS > 1 ? NS - 1 : 1;
+            const int sl = NS > 1 ? s - 1 : 0;
 #pragma unroll
-            for (int q = s * NPAIR / NS; q < (s + 1) * NPAIR / NS; ++q) {
+            for (int q = sl < 0 ? 0 : sl * NPAIR / NSL; q < (sl < 0 ? 0 : (sl + 1) * NPAIR / NSL); ++q) {
                 const int e = 2 * q, i = e / (WNG * 16), j = (e / 16) % WNG, r = e % 16;
                 mprev = fmaxf(mprev, fmaxf(fabsf(prev[i][j][r]), fabsf(prev[i][j][r + 1])));
             }
@@ -176,7 +216,8 @@ __device__ __forceinline__ void sk_group(const char* smem, int jg, int l32, int 
 template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC>
 __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, int64_t ab, int64_t col0, int l32,
                                          int half, bool self, int32_t nb, const uint4 (&av)[PARTS][WM][KV / 2],
-                                         sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg) {
+                                         sk_f16 (&acc)[WM][WNG], float& lane_best, int& lane_ab, int& lane_jg,
+                                         uint4 (&bv)[PARTS][WNG][KV / 2]) {
     const int64_t row0 = ab * 32 * WM;
     const bool edge_rows = row0 + 32 * WM > g.na;
     constexpr bool DBUF = sk_dbuf(PARTS, WM, WNG, KV / 2, PF, OCC);
@@ -186,14 +227,18 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
         constexpr int NG = BN / 32 / WNG;
         sk_f16 acc2[WM][WNG];
         float unused = 0.0f;
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, 0, l32, half, av, acc, acc, unused);
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, 0, NG > 1 ? WNG : 0, l32, half, av, acc, acc,
+                                                                   unused, bv);
 #pragma unroll
         for (int q = 1; q < NG; ++q) {
             float m = -1.0f;
+            const int nx = (q + 1 < NG) ? (q + 1) * WNG : 0;  // after the last group: the next block's first
             if (q & 1)
-                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, l32, half, av, acc2, acc, m);
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, nx, l32, half, av, acc2, acc,
+                                                                          m, bv);
             else
-                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, l32, half, av, acc, acc2, m);
+                sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, true>(smem, q * WNG, nx, l32, half, av, acc, acc2,
+                                                                          m, bv);
             if (m > lane_best) {
                 lane_best = m;
                 lane_ab = (int)ab;
@@ -218,7 +263,8 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
     float unused = 0.0f;
 #pragma unroll 1
     for (int jg = 0; jg < BN / 32; jg += WNG) {
-        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, l32, half, av, acc, acc, unused);
+        const int nx = (jg + WNG < BN / 32) ? jg + WNG : 0;
+        sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, nx, l32, half, av, acc, acc, unused, bv);
         const int32_t c0 = (int32_t)(col0 + jg * 32);
         const bool edge = edge_rows || (c0 + 32 * WNG > nb) || self;
         float m = -1.0f;
@@ -257,7 +303,8 @@ __device__ __forceinline__ void sk_block(const GemmArgs& g, const char* smem, in
 template <int PREC, int PARTS, int WM, int WNG, int KV, int BN, int ROWB, int PF, int OCC>
 __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, int64_t col0, int lane, int l32,
                                           int half, bool self, int32_t nb, int64_t rowb_g, float lane_best, int lane_ab,
-                                          int lane_jg, uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG]) {
+                                          int lane_jg, uint4 (&av)[PARTS][WM][KV / 2], sk_f16 (&acc)[WM][WNG],
+                                          uint4 (&bv)[PARTS][WNG][KV / 2]) {
     const float wb = sk_wave_max(lane_best);
     if (wb < 0.0f) return;
     int code = (lane_best == wb) ? lane_ab * (BN / 32) + lane_jg : 0x7fffffff;
@@ -270,7 +317,8 @@ __device__ __forceinline__ void sk_finish(const GemmArgs& g, const char* smem, i
     const int64_t row0 = (int64_t)ab * 32 * WM;
     sk_load_a<PARTS, WM, KV>(g, row0, l32, half, rowb_g, av);
     float unused = 0.0f;
-    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, l32, half, av, acc, acc, unused);
+    sk_prologue<PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(smem, jg, l32, half, bv);
+    sk_group<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC, false>(smem, jg, jg, l32, half, av, acc, acc, unused, bv);
     const int32_t c0 = (int32_t)(col0 + jg * 32);
     uint32_t cand = 0xffffffffu, neg = 0;
 #pragma unroll
@@ -339,6 +387,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n
     const int64_t it_end = items * (r + 1) / R;
 
     uint4 av[PARTS][WM][KV / 2];
+    uint4 bv[PARTS][WNG][KV / 2];
     sk_f16 acc[WM][WNG];
     while (it < it_end) {
         const int64_t tj = t0 + it / na_x;
@@ -352,19 +401,36 @@ __global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n
         // previous run's tile until every wave has finished with it
         __syncthreads();
         {
+            // every thread copies NV / 256 vectors per part (BN * KV is a
+            // multiple of 256 for every configuration); up to 8 loads are
+            // issued before their stores, so a run's staging costs a few
+            // memory round trips instead of one per vector
             constexpr int NV = BN * KV;  // 16-byte vectors per part
+            constexpr int PER = NV / 256, CH = sk_batch(PER);
+            static_assert(NV % 256 == 0, "B tile staging: whole vectors per thread");
+            // the tile's global rows are contiguous (row pitch KV * 16 bytes):
+            // vector v sits at v * 16; in LDS each row is padded by 16 bytes
 #pragma unroll
             for (int q = 0; q < PARTS; ++q) {
-                const char* src = (const char*)(q ? g.b_lo : g.b_hi) + col0 * rowb_g;
+                const uint4* src = reinterpret_cast<const uint4*>((const char*)(q ? g.b_lo : g.b_hi) + col0 * rowb_g);
                 char* dst = smem + q * BN * ROWB;
-                for (int v = tid; v < NV; v += 256) {
-                    int row = v / KV, c = v - row * KV;
-                    *reinterpret_cast<uint4*>(dst + row * ROWB + c * 16) =
-                        *reinterpret_cast<const uint4*>(src + row * rowb_g + c * 16);
+#pragma unroll
+                for (int u0 = 0; u0 < PER; u0 += CH) {
+                    uint4 tmp[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) tmp[u] = src[tid + (u0 + u) * 256];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int v = tid + (u0 + u) * 256;
+                        *reinterpret_cast<uint4*>(dst + (v + v / KV) * 16) = tmp[u];
+                    }
                 }
             }
         }
         __syncthreads();
+
+        // the run's first group: its first D steps of B fragments
+        sk_prologue<PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(smem, 0, l32, half, bv);
 
         // Per-lane running maximum and the (A block, column group) where it
         // first occurred; no cross-lane work inside the sweep.
@@ -374,7 +440,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n
             for (int64_t ab = ab0 + wave; ab < ab1; ab += 4) {
                 sk_load_a<PARTS, WM, KV>(g, ab * 32 * WM, l32, half, rowb_g, av);
                 sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av, acc,
-                                                                 lane_best, lane_ab, lane_jg);
+                                                                 lane_best, lane_ab, lane_jg, bv);
             }
         } else {
             // A fragments double-buffered in registers: the next block's
@@ -391,17 +457,17 @@ __global__ __launch_bounds__(256, OCC) void gemm_smallk_kernel(GemmArgs g, int n
             while (ab < ab1) {
                 sk_load_a<PARTS, WM, KV>(g, min(ab + 4, ab_last) * 32 * WM, l32, half, rowb_g, av2);
                 sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av, acc,
-                                                                 lane_best, lane_ab, lane_jg);
+                                                                 lane_best, lane_ab, lane_jg, bv);
                 ab += 4;
                 if (ab >= ab1) break;
                 sk_load_a<PARTS, WM, KV>(g, min(ab + 4, ab_last) * 32 * WM, l32, half, rowb_g, av);
                 sk_block<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, ab, col0, l32, half, self, nb, av2, acc,
-                                                                 lane_best, lane_ab, lane_jg);
+                                                                 lane_best, lane_ab, lane_jg, bv);
                 ab += 4;
             }
         }
         sk_finish<PREC, PARTS, WM, WNG, KV, BN, ROWB, PF, OCC>(g, smem, col0, lane, l32, half, self, nb, rowb_g, lane_best,
-                                                          lane_ab, lane_jg, av, acc);
+                                                          lane_ab, lane_jg, av, acc, bv);
         it += run;
     }
 }
