@@ -260,19 +260,23 @@ def measure_peaks(torch, pc, reps=3):
 
     it_lds, it_mfma, it_f32, it_f64 = 3000, 10000, 20000, 40000
     lds = nb * 256 * it_lds * 128 / best_s(lambda: pc.corr_peak_lds(nb, it_lds, oi))
-    mfma = nb * 4 * it_mfma * 4 * 32768 / best_s(lambda: pc.corr_peak_mfma_f16(nb, it_mfma, o32))
+    mfma = nb * 4 * it_mfma * 4 * 32768 / best_s(lambda: pc.corr_peak_mfma_f16(nb, it_mfma, o32, random_operands=True))
+    mfma_c = nb * 4 * it_mfma * 4 * 32768 / best_s(lambda: pc.corr_peak_mfma_f16(nb, it_mfma, o32, random_operands=False))
     f32 = nb * 256 * it_f32 * 16 * 2 / best_s(lambda: pc.corr_peak_valu_f32(nb, it_f32, o32))
     med3 = nb * 256 * it_f32 * 16 / best_s(lambda: pc.corr_peak_valu_med3(nb, it_f32, o32))
     f64 = nb * 256 * it_f64 * 8 * 2 / best_s(lambda: pc.corr_peak_valu_f64(nb, it_f64, o64))
     hb = hbm.numel() / best_s(lambda: pc.corr_peak_hbm_read(hbm, nb, oi))
     del hbm
-    return {"lds_read_TBps": lds / 1e12, "mfma_f16_TFLOPs": mfma / 1e12, "valu_f32_fma_TFLOPs": f32 / 1e12,
+    return {"lds_read_TBps": lds / 1e12, "mfma_f16_TFLOPs": mfma / 1e12,
+            "mfma_f16_TFLOPs_repeated_operands": mfma_c / 1e12, "valu_f32_fma_TFLOPs": f32 / 1e12,
             "valu_lane_ops_Tops": f32 / 2 / 1e12, "valu_med3_lane_ops_Tops": med3 / 1e12,
             "valu_f64_fma_TFLOPs": f64 / 1e12, "hbm_read_GBps": hb / 1e9,
             "vendor": {"lds_read_TBps": 78.6, "mfma_f16_TFLOPs": 2500.0, "valu_lane_ops_Tops": 78.6432,
                        "valu_f64_fma_TFLOPs": 78.6, "hbm_read_GBps": 8000.0},
             "method": "corr_peak_* probes, 2048 workgroups of 256 threads, best of 3 launches (HIP events); "
-                      "VALU without packed FP32 (lane-ops = FMA flops / 2)"}
+                      "MFMA on random full-mantissa operands (the power-limited rate that applies to "
+                      "standardised data; small repeated operands beside); VALU without packed FP32 "
+                      "(lane-ops = FMA flops / 2)"}
 
 
 def with_measured_peak(roof, peaks):

@@ -34,8 +34,12 @@ int corr_peak_lds(int n_blocks, int iters, unsigned int* out, void* stream);
 
 /* Dense FP16 matrix cores: every wave of n_blocks 256-thread workgroups issues
  * iters * 4 v_mfma_f32_32x32x16_f16 (four independent accumulators).
- * Work: n_blocks * 4 * iters * 4 * 32768 flops. out: float. */
-int corr_peak_mfma_f16(int n_blocks, int iters, float* out, void* stream);
+ * random_operands = 0: small repeated operand values (the unit's best case);
+ * 1: pseudo-random full-mantissa values in (-1, 1), like standardised
+ * ensemble data -- the matrix cores draw more power on such data and the
+ * clock drops, so this is the ceiling that applies to the correlation
+ * contraction. Work: n_blocks * 4 * iters * 4 * 32768 flops. out: float. */
+int corr_peak_mfma_f16(int n_blocks, int iters, int random_operands, float* out, void* stream);
 
 /* FP32 vector FMA (unpacked: the library is built without packed FP32):
  * every thread runs 16 independent chains of iters fmaf.

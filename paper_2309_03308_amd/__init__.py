@@ -560,9 +560,11 @@ def corr_peak_lds(n_blocks: int, iters: int, out, stream=None):
     _peak("corr_peak_lds", n_blocks, iters, out, stream, ("int32", "uint32"))
 
 
-def corr_peak_mfma_f16(n_blocks: int, iters: int, out, stream=None):
-    """FP16 MFMA probe; out: device float32, >= n_blocks * 256."""
-    _peak("corr_peak_mfma_f16", n_blocks, iters, out, stream)
+def corr_peak_mfma_f16(n_blocks: int, iters: int, out, random_operands: bool = True, stream=None):
+    """FP16 MFMA probe (random full-mantissa operands, or small repeated ones); out: device float32."""
+    _peak_out(out, n_blocks, ("float32",))
+    _lib.check(_lib.load().corr_peak_mfma_f16(int(n_blocks), int(iters), 1 if random_operands else 0,
+                                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
 
 
 def corr_peak_valu_f32(n_blocks: int, iters: int, out, stream=None):

@@ -118,7 +118,7 @@ SIGNATURES = {
     "corr_proposal_inputs": (_I, [_P, ctypes.POINTER(corr_field), ctypes.POINTER(corr_region), _I32, _P, _I32, _I32,
                                   _I32, _I32, _P, _P, _P]),
     "corr_peak_lds": (_I, [_I, _I, _P, _P]),
-    "corr_peak_mfma_f16": (_I, [_I, _I, _P, _P]),
+    "corr_peak_mfma_f16": (_I, [_I, _I, _I, _P, _P]),
     "corr_peak_valu_f32": (_I, [_I, _I, _P, _P]),
     "corr_peak_valu_med3": (_I, [_I, _I, _P, _P]),
     "corr_peak_valu_f64": (_I, [_I, _I, _P, _P]),

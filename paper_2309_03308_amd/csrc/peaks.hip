@@ -40,13 +40,30 @@ __global__ __launch_bounds__(PT) void peak_lds_kernel(int iters, unsigned int* o
 typedef _Float16 pk_h8 __attribute__((ext_vector_type(8)));
 typedef float pk_f16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(PT) void peak_mfma_f16_kernel(int iters, float* out) {
+// A 32-bit mixing hash (multiply / xor-shift rounds) for the probe's operands.
+__device__ __forceinline__ unsigned int pk_mix(unsigned int h) {
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+__global__ __launch_bounds__(PT) void peak_mfma_f16_kernel(int iters, int random_operands, float* out) {
     const int t = threadIdx.x;
     pk_h8 a, b;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        a[e] = (_Float16)(0.001f * (float)((t + e) & 7));
-        b[e] = (_Float16)(0.002f * (float)((t * 3 + e) & 7));
+        if (random_operands) {
+            const unsigned int h = pk_mix((blockIdx.x * PT + t) * 16u + 2u * e);
+            const unsigned int k = pk_mix((blockIdx.x * PT + t) * 16u + 2u * e + 1u);
+            a[e] = (_Float16)((float)(h & 0xffffu) * (1.0f / 32768.0f) - 1.0f);
+            b[e] = (_Float16)((float)(k & 0xffffu) * (1.0f / 32768.0f) - 1.0f);
+        } else {
+            a[e] = (_Float16)(0.001f * (float)((t + e) & 7));
+            b[e] = (_Float16)(0.002f * (float)((t * 3 + e) & 7));
+        }
     }
     pk_f16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
     for (int it = 0; it < iters; ++it) {
@@ -157,9 +174,9 @@ int corr_peak_lds(int n_blocks, int iters, unsigned int* out, void* stream) {
     return CORR_OK;
 }
 
-int corr_peak_mfma_f16(int n_blocks, int iters, float* out, void* stream) {
+int corr_peak_mfma_f16(int n_blocks, int iters, int random_operands, float* out, void* stream) {
     if (int rc = check_args(n_blocks, iters, out)) return rc;
-    peak_mfma_f16_kernel<<<n_blocks, PT, 0, (hipStream_t)stream>>>(iters, out);
+    peak_mfma_f16_kernel<<<n_blocks, PT, 0, (hipStream_t)stream>>>(iters, random_operands ? 1 : 0, out);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }

@@ -109,6 +109,7 @@ def test_peak_probes(env):
     pc.corr_peak_hbm_read(buf, nb, oi)
     torch.cuda.synchronize()
     assert _status(lambda: pc.corr_peak_lds(0, 4, oi), pc) == lib.CORR_EINVAL
+    pc.corr_peak_mfma_f16(nb, 10, o32, random_operands=False)
     assert _status(lambda: pc.corr_peak_mfma_f16(nb, 0, o32), pc) == lib.CORR_EINVAL
     assert _status(lambda: pc.corr_peak_hbm_read(buf[1:5], nb, oi), pc) == lib.CORR_EINVAL  # misaligned
     with pytest.raises(ValueError):  # fewer than n_blocks * 256 words: refused by the binding
