@@ -240,6 +240,9 @@ int corr_ksg_mi_pairs_prepared(corr_ctx* ctx, const corr_prepared* A, const corr
  * When A and B are the same field, pA == pB is skipped. Ties go to the
  * smallest (local pA, local pB) for exhaustive runs. prec applies to
  * Pearson; k to KSG. out: HOST pointer; the call synchronises `stream`.
+ * An exhaustive call over 2^31 or more point pairs runs as consecutive
+ * pieces of ra (same result and tie-break as one pass); a sampled call over
+ * such a region pair returns CORR_EUNSUPPORTED.
  */
 int corr_region_max(corr_ctx* ctx, const corr_field* A, const corr_region* ra, const corr_field* B,
                     const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,

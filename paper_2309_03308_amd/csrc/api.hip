@@ -947,6 +947,62 @@ int corr_box_pairs_max(corr_ctx* ctx, const corr_prepared* A, const corr_prepare
 // with its workspaces taken from `w`.
 static int region_max_impl(Ws& w, const corr_field* A, const corr_region* ra, const corr_field* B,
                            const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
+                           int64_t n_samples, corr_max* out, hipStream_t s);
+
+// Exhaustive maximum over 2^31 or more point pairs (Sec. 3: the maximum over
+// every pA in A and pB in B): region A is cut into consecutive pieces of its
+// local x-fastest order -- z slabs, or y rows of one z layer, or x runs of
+// one row when a layer or a row alone is too large -- each small enough for
+// the 31-bit pair index, and each piece runs as an ordinary exhaustive call.
+// Pieces cover increasing ranges of A's local index, so keeping the first
+// piece among equal maxima keeps the smallest local pair index, the same
+// tie-break as one call; n_evaluated adds up.
+static int region_max_split(Ws& w, const corr_field* A, const corr_region* ra, const corr_field* B,
+                            const corr_region* rb, int measure, int prec, int32_t k, corr_max* out,
+                            hipStream_t s) {
+    const int64_t nb = (int64_t)rb->dx * rb->dy * rb->dz;
+    const int64_t cap = ((int64_t(1) << 31) - 1) / nb;  // points of A per piece (>= 1: nb < 2^31)
+    const int64_t layer = (int64_t)ra->dx * ra->dy;
+    corr_max best{};
+    best.pa = best.pb = -1;
+    bool have = false;
+    int64_t evaluated = 0;
+    auto piece = [&](const corr_region& sub) -> int {
+        corr_max part{};
+        const int rc = region_max_impl(w, A, &sub, B, rb, measure, prec, k, nullptr, 0, &part, s);
+        if (rc) return rc;
+        evaluated += part.n_evaluated;
+        if (part.pa >= 0 && (!have || part.value > best.value)) {
+            best = part;
+            have = true;
+        }
+        return CORR_OK;
+    };
+    int rc = CORR_OK;
+    if (layer <= cap) {
+        const int32_t tz = (int32_t)(cap / layer);
+        for (int32_t z = 0; z < ra->dz && !rc; z += tz)
+            rc = piece(corr_region{ra->x0, ra->y0, ra->z0 + z, ra->dx, ra->dy, std::min(tz, ra->dz - z)});
+    } else if ((int64_t)ra->dx <= cap) {
+        const int32_t ty = (int32_t)(cap / ra->dx);
+        for (int32_t z = 0; z < ra->dz && !rc; ++z)
+            for (int32_t y = 0; y < ra->dy && !rc; y += ty)
+                rc = piece(corr_region{ra->x0, ra->y0 + y, ra->z0 + z, ra->dx, std::min(ty, ra->dy - y), 1});
+    } else {
+        const int32_t tx = (int32_t)cap;
+        for (int32_t z = 0; z < ra->dz && !rc; ++z)
+            for (int32_t y = 0; y < ra->dy && !rc; ++y)
+                for (int32_t x = 0; x < ra->dx && !rc; x += tx)
+                    rc = piece(corr_region{ra->x0 + x, ra->y0 + y, ra->z0 + z, std::min(tx, ra->dx - x), 1, 1});
+    }
+    if (rc) return rc;
+    *out = best;
+    out->n_evaluated = evaluated;
+    return CORR_OK;
+}
+
+static int region_max_impl(Ws& w, const corr_field* A, const corr_region* ra, const corr_field* B,
+                           const corr_region* rb, int measure, int prec, int32_t k, const int32_t* sample_pairs,
                            int64_t n_samples, corr_max* out, hipStream_t s) {
     corr_ctx* ctx = w.ctx;
     if (!ctx) return fail(CORR_EINVAL, "null context");
@@ -970,7 +1026,12 @@ static int region_max_impl(Ws& w, const corr_field* A, const corr_region* ra, co
         return fail(CORR_EINVAL, "n_samples given without sample_pairs");
     Box ba = region_box(*ra, *A), bb = region_box(*rb, *B);
     const int64_t na = ba.count(), nb = bb.count();
-    if (na * nb >= (int64_t(1) << 31)) return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
+    if (na * nb >= (int64_t(1) << 31)) {
+        // the result key carries a 31-bit local pair index: an exhaustive
+        // call over more pairs runs as consecutive pieces of region A
+        if (sample_pairs != nullptr) return fail(CORR_EUNSUPPORTED, "region pair has 2^31 or more point pairs");
+        return region_max_split(w, A, ra, B, rb, measure, prec, k, out, s);
+    }
     if ((rc = ctx_use_stream(ctx, s))) return rc;
     const bool sf = same_field(*A, *B);
     memset(out, 0, sizeof(*out));
