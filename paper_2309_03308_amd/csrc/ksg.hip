@@ -6,7 +6,9 @@
 // the j != i with marginal distance strictly below eps_i; the estimate is
 // psi(M) + psi(k) - mean_i[psi(n_x,i + 1) + psi(n_y,i + 1)].
 //
-// Design (gfx950, wave64, VALU-bound):
+// Design (gfx950, wave64; bound by VALU issue, chiefly the insertion
+// network's v_med3_f32, which issues once per 4 cycles per SIMD where
+// add/sub/min/max/FMA issue about every 2.5):
 //  - every wave streams through its own contiguous range of pairs; the
 //    range's (pair, sample) items are laid densely over the lanes, 64 per
 //    trip, so a trip may cover the tail of one pair and the head of the next
