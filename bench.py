@@ -861,7 +861,7 @@ def large_legs(args, torch, synth, pc):
         "precision": "f16", "pairs": nf,
         "roofline": {"bound": "mfma", "achieved": fl / (g_ms / 1e3) / 1e12, "peak": MFMA_F16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": fl / (g_ms / 1e3) / MFMA_F16_PEAK, "traffic": None,
-                     "kernel": "gemm_max_kernel (K = 1008)", "work": "2 M flops per point pair"}}
+                     "kernel": "gemm_max_wide_kernel (256 x 256 tiles, K = 1024)", "work": "2 M flops per point pair"}}
 
     if not args.no_cpu_baseline:
         print("bench: oracle at M = 1000", file=sys.stderr, flush=True)

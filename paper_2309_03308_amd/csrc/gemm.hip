@@ -194,6 +194,107 @@ __device__ __forceinline__ void chunk_step(char* smem, int c, int n_chunks, int 
     __syncthreads();
 }
 
+// Fold |r| of one wave's WM x WN accumulator blocks (the block at (i, j)
+// covers rows r_base + 32 i .. and columns c_base + 32 j ..) into the wave's
+// running maximum `best` and its key. `edge`: the workgroup tile reaches past
+// the valid rows or columns (those are masked, as are self pairs).
+template <int WM, int WN>
+__device__ __forceinline__ void fold_tile(const f16_t (&acc)[WM][WN], const GemmArgs& g, int64_t r_base,
+                                          int64_t c_base, bool edge, int lane, float& best,
+                                          unsigned long long& best_key) {
+    const bool self = g.self_col != nullptr;
+    // 32x32 accumulator layout: register r of lane l holds
+    // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the block.
+#define ELEM_ROW(i, r) (r_base + (i) * 32 + 8 * ((r) >> 2) + 4 * (lane >> 5) + ((r) & 3))
+#define ELEM_COL(j) (c_base + (j) * 32 + (lane & 31))
+    const bool fast = !edge && !self;  // every element valid
+    float m = -1.0f;
+    float mb[WM][WN];                  // per-block maxima (fast case)
+    if (fast) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                float x = -1.0f;
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) x = fmaxf(x, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
+                mb[i][j] = x;
+                m = fmaxf(m, x);
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
+                    bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
+                    if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
+                }
+    }
+    const float wm = wave_max(m);
+    if (wm >= 0.0f && wm >= best) {
+        // locate: smallest linear index among elements with |r| == wm
+        uint32_t cand = 0xffffffffu;
+        uint32_t neg = 0;
+        if (fast) {
+            // Only the blocks holding wm are scanned, behind a wave-uniform
+            // branch, so the code of the others is neither run nor fetched.
+            // In a block (one column per lane) the smallest register index
+            // is the smallest row; across blocks the smallest index wins.
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) {
+                    if (__builtin_amdgcn_ballot_w64(mb[i][j] == wm) == 0) continue;
+                    int rr = -1;
+                    float sv = 0.0f;
+#pragma unroll
+                    for (int r = 15; r >= 0; --r) {
+                        const float v = acc[i][j][r];
+                        const bool hit = fabsf(v) == wm;
+                        rr = hit ? r : rr;
+                        sv = hit ? v : sv;
+                    }
+                    if (rr >= 0) {
+                        const uint32_t lin = (uint32_t)(ELEM_ROW(i, rr) * g.nb + ELEM_COL(j));
+                        if (lin < cand) {
+                            cand = lin;
+                            neg = sv < 0.0f ? 1u : 0u;
+                        }
+                    }
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        float v = acc[i][j][r];
+                        int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
+                        bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
+                        uint32_t lin = (uint32_t)(row * g.nb + col);
+                        if (ok && fabsf(v) == wm && lin < cand) {
+                            cand = lin;
+                            neg = v < 0.0f ? 1u : 0u;
+                        }
+                    }
+        }
+        unsigned long long k = (cand == 0xffffffffu) ? 0ull : make_key(wm, cand, neg);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            unsigned long long o = __shfl_xor(k, off, 64);
+            k = o > k ? o : k;
+        }
+        best_key = k > best_key ? k : best_key;
+        best = wm;
+    }
+#undef ELEM_ROW
+#undef ELEM_COL
+}
+
 template <int PREC>
 __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int n_ti, int n_tj) {
     using T = GemmTraits<PREC>;
@@ -269,63 +370,191 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
 #undef CHUNK
 
         // ---- epilogue: fold |r| of this tile into the wave's running max
-        const bool edge = (row0 + G_BM > g.na) || (col0 + G_BN > g.nb);
-        const bool self = g.self_col != nullptr;
-        // 32x32 accumulator layout: register r of lane l holds
-        // row 8*(r/4) + 4*(l/32) + r%4, column l%32 of the block.
-#define ELEM_ROW(i, r) (row0 + wr * 64 + (i) * 32 + 8 * ((r) >> 2) + 4 * (lane >> 5) + ((r) & 3))
-#define ELEM_COL(j) (col0 + wc * 32 * G_WN + (j) * 32 + (lane & 31))
-        float m = -1.0f;
-        if (!edge && !self) {
+        fold_tile<G_WM, G_WN>(acc, g, row0 + wr * 64, col0 + wc * 32 * G_WN,
+                              (row0 + G_BM > g.na) || (col0 + G_BN > g.nb), lane, best, best_key);
+    }
+    if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
+}
+
+// ---- wide tiles: single-pass 16-bit operands, enough tiles to fill the chip
+//
+// A workgroup tile of 256 x 256 (four waves in a 2 x 2 grid, each 128 x 128 =
+// 4 x 4 blocks of 32x32x16 MFMAs, 256 accumulator registers) reads each A
+// and B row once per 256 partner rows instead of once per 128: half the L2
+// traffic per product of the 128 x 128 tile, and one 16-byte LDS fragment
+// read per two MFMAs instead of one per MFMA. K is consumed in 32-element
+// chunks (64 B per row) through a ring of three LDS stages: during chunk c
+// the waves read stage c mod 3 (the chunk's second K-step) and stage
+// (c + 1) mod 3 (the next chunk's first K-step, read while this chunk's
+// products run), and copy chunk c + 2 into stage (c + 2) mod 3, whose last
+// readers finished before the barrier that ended chunk c - 1 -- one barrier
+// per chunk. Four register sets hold the global loads of chunks c + 2 to
+// c + 5, issued four chunks before their copy into LDS (a load from L2 under
+// this traffic takes longer than two chunks of products).
+constexpr int W_BM = 256, W_BN = 256;                   // workgroup tile
+constexpr int W_WM = 4, W_WN = 4;                       // 32x32 blocks per wave
+constexpr int W_KC = 32;                                // chunk length (elements)
+constexpr int W_QW = W_KC * 2 / 16;                     // 16-byte words per row and chunk
+constexpr int W_ROWB = W_KC * 2 + 16;                   // padded LDS row bytes (conflict-free reads)
+constexpr int W_STAGE = (W_BM + W_BN) * W_ROWB;         // bytes per LDS stage
+constexpr int W_NST = 3;                                // LDS stages
+constexpr int W_PF = 4;                                 // register sets of staged loads
+constexpr int W_NR = (W_BM + W_BN) * W_QW / G_THREADS;  // staged words per thread and chunk
+constexpr int W_RSTEP = G_THREADS / W_QW;               // rows between a thread's staged words
+static_assert(W_NR == 8 && W_RSTEP == 64, "staging layout: 4 A words, then 4 B words");
+
+__device__ __forceinline__ void w_load(const char* const (&src)[W_NR], int c, u4_t (&set)[W_NR]) {
 #pragma unroll
-            for (int i = 0; i < G_WM; ++i)
+    for (int r = 0; r < W_NR; ++r) set[r] = *reinterpret_cast<const u4_t*>(src[r] + c * (W_KC * 2));
+}
+
+__device__ __forceinline__ void w_store(char* dst, const u4_t (&set)[W_NR]) {
 #pragma unroll
-                for (int j = 0; j < G_WN; ++j)
+    for (int r = 0; r < W_NR; ++r) *reinterpret_cast<u4_t*>(dst + r * W_RSTEP * W_ROWB) = set[r];
+}
+
+// Fragments of K-step s (16 elements) of the chunk held in stage `st`.
+__device__ __forceinline__ void w_frags(const char* st, int wr, int wc, int lane, int s, u4_t (&fa)[W_WM],
+                                        u4_t (&fb)[W_WN]) {
+    const int off = (s * 16 + (lane >> 5) * 8) * 2;
+    const char* pa = st + (wr * 128 + (lane & 31)) * W_ROWB + off;
+    const char* pb = st + (W_BM + wc * 128 + (lane & 31)) * W_ROWB + off;
 #pragma unroll
-                    for (int r = 0; r < 16; r += 2) m = fmaxf(m, fmaxf(fabsf(acc[i][j][r]), fabsf(acc[i][j][r + 1])));
-        } else {
+    for (int i = 0; i < W_WM; ++i) fa[i] = *reinterpret_cast<const u4_t*>(pa + i * 32 * W_ROWB);
 #pragma unroll
-            for (int i = 0; i < G_WM; ++i)
+    for (int j = 0; j < W_WN; ++j) fb[j] = *reinterpret_cast<const u4_t*>(pb + j * 32 * W_ROWB);
+}
+
+// Instruction order of one chunk, for the scheduler: each of the 32 MFMAs
+// is followed by one memory instruction (the next K-step's fragment reads,
+// the LDS copy of a later chunk, its global loads), so the matrix pipe
+// is never left idle while a block of memory instructions issues (one wave
+// per SIMD: no other wave fills the gaps).
+__device__ __forceinline__ void w_schedule() {
+    constexpr int MFMA = 0x008, DS_READ = 0x100, DS_WRITE = 0x200, VMEM_READ = 0x020;
 #pragma unroll
-                for (int j = 0; j < G_WN; ++j)
+    for (int k = 0; k < 8; ++k) {
+        __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(DS_READ, 1, 0);
+    }
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
-                        bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
-                        if (ok) m = fmaxf(m, fabsf(acc[i][j][r]));
-                    }
+    for (int k = 0; k < 8; ++k) {
+        __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(DS_WRITE, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(VMEM_READ, 1, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(DS_READ, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(MFMA, 8, 0);
+}
+
+template <int PREC>
+__device__ __forceinline__ void w_mfma(f16_t (&acc)[W_WM][W_WN], const u4_t (&fa)[W_WM], const u4_t (&fb)[W_WN]) {
+#pragma unroll
+    for (int i = 0; i < W_WM; ++i)
+#pragma unroll
+        for (int j = 0; j < W_WN; ++j) {
+            if constexpr (PREC == CORR_PREC_BF16)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8_t, fa[i]),
+                                                                     __builtin_bit_cast(b8_t, fb[j]), acc[i][j], 0, 0, 0);
+            else
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8_t, fa[i]),
+                                                                    __builtin_bit_cast(h8_t, fb[j]), acc[i][j], 0, 0, 0);
         }
-        const float wm = wave_max(m);
-        if (wm >= 0.0f && wm >= best) {
-            // locate: smallest linear index among elements with |r| == wm
-            uint32_t cand = 0xffffffffu;
-            uint32_t neg = 0;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g, int n_ti, int n_tj) {
+    static_assert(PREC == CORR_PREC_F16 || PREC == CORR_PREC_BF16, "single-pass 16-bit operands");
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int64_t rowb_g = g.K * 2;
+    const int n_chunks = (int)(g.K / W_KC);  // a multiple of W_PF: K is a multiple of W_PF * W_KC
+    const int last = n_chunks - 1;
+    const int64_t n_tiles = (int64_t)n_ti * n_tj;
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    const int lg = (G % 8 == 0) ? ((b % 8) * (G / 8) + b / 8) : b;  // XCD-grouped, as above
+
+    // this thread stages the 16-byte word tid % 4 of rows tid / 4 + 64 r
+    const int trow = tid / W_QW;
+    char* const dst0 = smem + trow * W_ROWB + (tid % W_QW) * 16;
+
+    float best = -1.0f;
+    unsigned long long best_key = 0;
+
+    for (int64_t tile = lg; tile < n_tiles; tile += G) {
+        const int64_t grp = tile / (8 * (int64_t)n_tj);
+        const int first = (int)grp * 8, gsz = min(n_ti - first, 8);
+        const int64_t in = tile - grp * 8 * (int64_t)n_tj;
+        const int ti = first + (int)(in % gsz), tj = (int)(in / gsz);
+        const int64_t row0 = (int64_t)ti * W_BM, col0 = (int64_t)tj * W_BN;
+
+        // source rows, clamped to the padded row counts: a 256-row tile may
+        // run past buffers padded to 128 rows; rows past na / nb are masked
+        // in the epilogue
+        const char* src[W_NR];
 #pragma unroll
-            for (int i = 0; i < G_WM; ++i)
-#pragma unroll
-                for (int j = 0; j < G_WN; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        float v = acc[i][j][r];
-                        int64_t row = ELEM_ROW(i, r), col = ELEM_COL(j);
-                        bool ok = row < g.na && col < g.nb && !(self && g.self_col[row] == col);
-                        uint32_t lin = (uint32_t)(row * g.nb + col);
-                        if (ok && fabsf(v) == wm && lin < cand) {
-                            cand = lin;
-                            neg = v < 0.0f ? 1u : 0u;
-                        }
-                    }
-            unsigned long long k = (cand == 0xffffffffu) ? 0ull : make_key(wm, cand, neg);
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                unsigned long long o = __shfl_xor(k, off, 64);
-                k = o > k ? o : k;
-            }
-            best_key = k > best_key ? k : best_key;
-            best = wm;
+        for (int r = 0; r < W_NR / 2; ++r) {
+            const int64_t ra = min(row0 + trow + W_RSTEP * r, g.na_pad - 1);
+            const int64_t rb = min(col0 + trow + W_RSTEP * r, g.nb_pad - 1);
+            src[r] = (const char*)g.a_hi + ra * rowb_g + (tid % W_QW) * 16;
+            src[W_NR / 2 + r] = (const char*)g.b_hi + rb * rowb_g + (tid % W_QW) * 16;
         }
-#undef ELEM_ROW
-#undef ELEM_COL
+
+        u4_t set0[W_NR], set1[W_NR], set2[W_NR], set3[W_NR];
+        w_load(src, 0, set0);
+        w_load(src, min(1, last), set1);
+        w_store(dst0, set0);
+        w_load(src, min(2, last), set0);
+        w_store(dst0 + W_STAGE, set1);
+        w_load(src, min(3, last), set1);
+        w_load(src, min(4, last), set2);
+        w_load(src, min(5, last), set3);
+        __syncthreads();
+
+        f16_t acc[W_WM][W_WN];
+#pragma unroll
+        for (int i = 0; i < W_WM; ++i)
+#pragma unroll
+            for (int j = 0; j < W_WN; ++j) acc[i][j] = f16_t{};
+        u4_t fa0[W_WM], fb0[W_WN], fa1[W_WM], fb1[W_WN];
+        w_frags(smem, wr, wc, lane, 0, fa0, fb0);
+
+        // chunk cc in stage st; `set` holds chunk cc + 2 and then takes
+        // cc + 2 + W_PF (the four sets hold chunks cc + 2 .. cc + 5).
+        // Past the last chunk the reads and copies touch idle stages and the
+        // loads re-read the last chunk (no branch: a branch here would make
+        // the compiler wait for every load in flight).
+        int st = 0;
+#define W_CHUNK(cc, set)                                                        \
+    {                                                                           \
+        const int sn = st == W_NST - 1 ? 0 : st + 1;                            \
+        const int sw = sn == W_NST - 1 ? 0 : sn + 1;                            \
+        w_frags(smem + st * W_STAGE, wr, wc, lane, 1, fa1, fb1);                \
+        w_mfma<PREC>(acc, fa0, fb0);                                            \
+        w_store(dst0 + sw * W_STAGE, set);                                      \
+        w_load(src, min((cc) + W_PF + 2, last), set);                           \
+        w_frags(smem + sn * W_STAGE, wr, wc, lane, 0, fa0, fb0);                \
+        w_mfma<PREC>(acc, fa1, fb1);                                            \
+        w_schedule();                                                           \
+        __syncthreads();                                                        \
+        st = sn;                                                                \
+    }
+        for (int c = 0; c < n_chunks; c += W_PF) {
+            W_CHUNK(c, set0);
+            W_CHUNK(c + 1, set1);
+            W_CHUNK(c + 2, set2);
+            W_CHUNK(c + 3, set3);
+        }
+#undef W_CHUNK
+
+        fold_tile<W_WM, W_WN>(acc, g, row0 + wr * 128, col0 + wc * 128,
+                              (row0 + W_BM > g.na) || (col0 + W_BN > g.nb), lane, best, best_key);
     }
     if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
 }
@@ -346,8 +575,34 @@ static int launch_p(const GemmArgs& g, int num_cus, hipStream_t s) {
     return CORR_OK;
 }
 
+template <int PREC>
+static int launch_wide(const GemmArgs& g, int64_t n_ti, int64_t n_tj, int num_cus, hipStream_t s) {
+    const int64_t n_tiles = n_ti * n_tj;
+    const int grid = (int)(n_tiles < num_cus ? n_tiles : num_cus);
+    const size_t lds = (size_t)W_NST * W_STAGE;
+    if (g.K <= 0 || g.K % (W_PF * W_KC)) return fail(CORR_EINVAL, "contraction: K not a multiple of the chunk group");
+    int rc = kernel_setup((const void*)gemm_max_wide_kernel<PREC>, lds, G_THREADS, nullptr);
+    if (rc) return rc;
+    gemm_max_wide_kernel<PREC><<<dim3((unsigned)grid), G_THREADS, lds, s>>>(g, (int)n_ti, (int)n_tj);
+    CORR_LAUNCH_CHECK();
+    return CORR_OK;
+}
+
+// Wide 256 x 256 tiles when there are enough of them to give every CU one;
+// otherwise (and for FP32 and the split modes) the 128 x 128 tiles.
+static bool use_wide(const GemmArgs& g, int num_cus, int64_t& n_ti, int64_t& n_tj) {
+    if (g.prec != CORR_PREC_F16 && g.prec != CORR_PREC_BF16) return false;
+    n_ti = (g.na + W_BM - 1) / W_BM;
+    n_tj = (g.nb + W_BN - 1) / W_BN;
+    return n_ti * n_tj >= num_cus;
+}
+
 int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s) {
     if (g.na == 0 || g.nb == 0) return CORR_OK;
+    int64_t n_ti = 0, n_tj = 0;
+    if (use_wide(g, num_cus, n_ti, n_tj))
+        return g.prec == CORR_PREC_F16 ? launch_wide<CORR_PREC_F16>(g, n_ti, n_tj, num_cus, s)
+                                       : launch_wide<CORR_PREC_BF16>(g, n_ti, n_tj, num_cus, s);
     switch (g.prec) {
         case CORR_PREC_F32: return launch_p<CORR_PREC_F32>(g, num_cus, s);
         case CORR_PREC_F16: return launch_p<CORR_PREC_F16>(g, num_cus, s);
