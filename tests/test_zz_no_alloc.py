@@ -93,6 +93,20 @@ def test_long_k_contraction_two_calls(env):
             _same(ctx.corr_region_max_noalloc(f, ra, rb, "pearson", prec), ctx.corr_region_max(f, ra, rb, "pearson", prec))
 
 
+def test_wide_tile_contraction_two_calls(env):
+    # M = 1000, two 16^3 bricks: 256 tiles of 256 x 256 (the wide-tile
+    # kernel); then a smaller ragged pair that takes the 128 x 128 kernel
+    pc, ctx, torch = env["pc"], env["ctx"], env["torch"]
+    rng = np.random.default_rng(9)
+    data = rng.standard_normal((1000, 32 * 16 * 16), dtype=np.float32)
+    f = pc.Field(torch.from_numpy(data).cuda(), 32, 16, 16)
+    for box in ((0, 0, 0, 16, 16, 16, 16, 0, 0, 16, 16, 16), (1, 0, 2, 15, 16, 13, 16, 3, 0, 14, 11, 16)):
+        ra, rb = pc.region(*box[:6]), pc.region(*box[6:])
+        for prec in ("f16", "bf16"):
+            _say(f"  noalloc wide-tile contraction {prec}, {box}")
+            _same(ctx.corr_region_max_noalloc(f, ra, rb, "pearson", prec), ctx.corr_region_max(f, ra, rb, "pearson", prec))
+
+
 def test_too_large_is_refused(env):
     torch, pc, ctx = env["torch"], env["pc"], env["ctx"]
     # KSG at M = 1000 over two 5000-point boxes: z rows, sorted rows and
