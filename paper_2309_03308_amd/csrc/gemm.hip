@@ -22,8 +22,13 @@
 //  - epilogue: per-lane max of |r| (v_max3 with abs modifiers), wave max by
 //    shuffles; only when a tile beats the wave's best so far (rare after the
 //    first tiles) does the wave locate the element, picking the smallest
-//    linear index among equal values. One 64-bit atomicMax per wave at the
-//    end publishes (|r|, index, sign) -- independent of scheduling order.
+//    linear index among equal values (the search scans only the 32 x 32
+//    blocks whose maximum equals the wave's). One 64-bit atomicMax per wave
+//    at the end publishes (|r|, index, sign) -- independent of scheduling
+//    order;
+//  - single-pass 16-bit operands on bricks large enough to give every CU a
+//    256 x 256 tile take the wide-tile kernel further down (one workgroup
+//    per CU, 128 x 128 per wave).
 #include "common.h"
 
 namespace corr {
