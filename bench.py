@@ -491,6 +491,19 @@ def run_large(args, torch, synth, pc):
     t_k = timed(lambda: ctx.corr_ksg_mi_pairs(f, pairs, k=10, out=out), max(1, args.steps // 10))
     t_g = timed(lambda: ctx.corr_region_max(f, ra, rb, "pearson", args.prec), args.steps)
     n_focus = 4096 * 4096
+    # two 32x32x20 regions (4.19e8 pairs): many 256x256 tiles per CU, so the
+    # contraction's per-tile start-up and epilogue are amortised; kernel time
+    # from HIP events on the call's stream
+    ctx.set_timing(True)
+    wa, wb = pc.region(0, 0, 0, 32, 32, 20), pc.region(64, 64, 0, 32, 32, 20)
+    n_wide = (32 * 32 * 20) ** 2
+    wide = {}
+    for wp in ("f16", "bf16"):
+        _, w_ms = _timed(torch, lambda: ctx.corr_region_max(f, wa, wb, "pearson", wp), max(3, args.steps // 2),
+                         args.warmup, ctx, "gemm")
+        wide[wp] = {"kernel_ms": w_ms, "pairs_per_s": n_wide / (w_ms / 1e3),
+                    "tflops_algorithmic": 2.0 * 1000 * n_wide / (w_ms / 1e3) / 1e12}
+    ctx.set_timing(False)
     ms = (t_p + t_k + t_g) * 1e3
     value = (2 * pairs.shape[0] + n_focus) / (ms / 1e3)
     line = _line(args, value, ms,
@@ -503,7 +516,8 @@ def run_large(args, torch, synth, pc):
                             "focus_tflops_algorithmic": 2.0 * 1000 * n_focus / t_g / 1e12,
                             # FP32 operand rows as gathered (1008 padded members, 4 B each, two rows
                             # per pair); the time also holds standardising the whole field
-                            "pearson_gather_gbps_fp32_rows": pairs.shape[0] * 2 * 1008 * 4 / t_p / 1e9})
+                            "pearson_gather_gbps_fp32_rows": pairs.shape[0] * 2 * 1008 * 4 / t_p / 1e9,
+                            "contraction_32x32x20_regions": wide})
     print(json.dumps(line), flush=True)
     ctx.close()
 
