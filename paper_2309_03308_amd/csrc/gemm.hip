@@ -485,8 +485,13 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
     const int b = blockIdx.x;
     const int lg = (G % 8 == 0) ? ((b % 8) * (G / 8) + b / 8) : b;  // XCD-grouped, as above
 
-    // this thread stages the 16-byte word tid % 4 of rows tid / 4 + 64 r
-    const int trow = tid / W_QW;
+    // this thread stages the 16-byte word tid % 4 of rows trow + 64 r. A
+    // wave's 16 lane groups of 4 take its 16 rows in the order 0, 4, 8, 12,
+    // 1, 5, ...: the LDS serves 16 lanes (four rows) at a time, and at the
+    // 80-byte row pitch rows r and r + 3 share banks, rows r, r + 4, r + 8,
+    // r + 12 do not (each group of 4 lanes still reads one 64-byte segment)
+    const int lg4 = (tid & 63) / W_QW;
+    const int trow = (tid >> 6) * 16 + (lg4 & 3) * 4 + (lg4 >> 2);
     char* const dst0 = smem + trow * W_ROWB + (tid % W_QW) * 16;
 
     float best = -1.0f;
