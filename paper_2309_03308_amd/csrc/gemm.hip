@@ -393,9 +393,9 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
 // (c + 1) mod 3 (the next chunk's first K-step, read while this chunk's
 // products run), and copy chunk c + 2 into stage (c + 2) mod 3, whose last
 // readers finished before the barrier that ended chunk c - 1 -- one barrier
-// per chunk. Four register sets hold the global loads of chunks c + 2 to
-// c + 5, issued four chunks before their copy into LDS (a load from L2 under
-// this traffic takes longer than two chunks of products).
+// per chunk. Two register sets hold the global loads of chunks c + 2 and
+// c + 3, issued two chunks before their copy into LDS (four sets measured
+// slower: more registers and twice the unrolled loop code).
 constexpr int W_BM = 256, W_BN = 256;                   // workgroup tile
 constexpr int W_WM = 4, W_WN = 4;                       // 32x32 blocks per wave
 constexpr int W_KC = 32;                                // chunk length (elements)
@@ -403,7 +403,7 @@ constexpr int W_QW = W_KC * 2 / 16;                     // 16-byte words per row
 constexpr int W_ROWB = W_KC * 2 + 16;                   // padded LDS row bytes (conflict-free reads)
 constexpr int W_STAGE = (W_BM + W_BN) * W_ROWB;         // bytes per LDS stage
 constexpr int W_NST = 3;                                // LDS stages
-constexpr int W_PF = 4;                                 // register sets of staged loads
+constexpr int W_PF = 2;                                 // register sets of staged loads
 constexpr int W_NR = (W_BM + W_BN) * W_QW / G_THREADS;  // staged words per thread and chunk
 constexpr int W_RSTEP = G_THREADS / W_QW;               // rows between a thread's staged words
 static_assert(W_NR == 8 && W_RSTEP == 64, "staging layout: 4 A words, then 4 B words");
@@ -516,15 +516,13 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
             src[W_NR / 2 + r] = (const char*)g.b_hi + rb * rowb_g + (tid % W_QW) * 16;
         }
 
-        u4_t set0[W_NR], set1[W_NR], set2[W_NR], set3[W_NR];
+        u4_t set0[W_NR], set1[W_NR];
         w_load(src, 0, set0);
         w_load(src, min(1, last), set1);
         w_store(dst0, set0);
         w_load(src, min(2, last), set0);
         w_store(dst0 + W_STAGE, set1);
         w_load(src, min(3, last), set1);
-        w_load(src, min(4, last), set2);
-        w_load(src, min(5, last), set3);
         __syncthreads();
 
         f16_t acc[W_WM][W_WN];
@@ -536,7 +534,7 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
         w_frags(smem, wr, wc, lane, 0, fa0, fb0);
 
         // chunk cc in stage st; `set` holds chunk cc + 2 and then takes
-        // cc + 2 + W_PF (the four sets hold chunks cc + 2 .. cc + 5).
+        // cc + 2 + W_PF (the two sets hold chunks cc + 2 and cc + 3).
         // Past the last chunk the reads and copies touch idle stages and the
         // loads re-read the last chunk (no branch: a branch here would make
         // the compiler wait for every load in flight).
@@ -558,8 +556,6 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
         for (int c = 0; c < n_chunks; c += W_PF) {
             W_CHUNK(c, set0);
             W_CHUNK(c + 1, set1);
-            W_CHUNK(c + 2, set2);
-            W_CHUNK(c + 3, set3);
         }
 #undef W_CHUNK
 
