@@ -383,11 +383,14 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
 
 // ---- wide tiles: single-pass 16-bit operands, enough tiles to fill the chip
 //
-// A workgroup tile of 256 x 256 (four waves in a 2 x 2 grid, each 128 x 128 =
-// 4 x 4 blocks of 32x32x16 MFMAs, 256 accumulator registers) reads each A
-// and B row once per 256 partner rows instead of once per 128: half the L2
-// traffic per product of the 128 x 128 tile, and one 16-byte LDS fragment
-// read per two MFMAs instead of one per MFMA. K is consumed in 32-element
+// A workgroup tile of 256 x 256 reads each A and B row once per 256 partner
+// rows instead of once per 128: half the L2 traffic per product of the
+// 128 x 128 tile. Four waves (2 x 2, each 128 x 128 = 4 x 4 blocks of
+// 32x32x16 MFMAs, 256 accumulator registers, one fragment read per two
+// MFMAs) when each CU gets one tile; eight waves (2 x 4, each 128 x 64, two
+// per SIMD, 0.75 reads per MFMA) when CUs get two or more, where the second
+// wave on a SIMD hides the first one's waits (about 10% faster there, 12%
+// slower at one tile per CU). K is consumed in 32-element
 // chunks (64 B per row) through a ring of three LDS stages: during chunk c
 // the waves read stage c mod 3 (the chunk's second K-step) and stage
 // (c + 1) mod 3 (the next chunk's first K-step, read while this chunk's
@@ -397,37 +400,49 @@ __global__ __launch_bounds__(G_THREADS, 2) void gemm_max_kernel(GemmArgs g, int 
 // c + 3, issued two chunks before their copy into LDS (four sets measured
 // slower: more registers and twice the unrolled loop code).
 constexpr int W_BM = 256, W_BN = 256;                   // workgroup tile
-constexpr int W_WM = 4, W_WN = 4;                       // 32x32 blocks per wave
+constexpr int W_WM = 4;                                 // 32x32 blocks per wave, rows
 constexpr int W_KC = 32;                                // chunk length (elements)
 constexpr int W_QW = W_KC * 2 / 16;                     // 16-byte words per row and chunk
 constexpr int W_ROWB = W_KC * 2 + 16;                   // padded LDS row bytes (conflict-free reads)
 constexpr int W_STAGE = (W_BM + W_BN) * W_ROWB;         // bytes per LDS stage
 constexpr int W_NST = 3;                                // LDS stages
 constexpr int W_PF = 2;                                 // register sets of staged loads
-constexpr int W_NR = (W_BM + W_BN) * W_QW / G_THREADS;  // staged words per thread and chunk
-constexpr int W_RSTEP = G_THREADS / W_QW;               // rows between a thread's staged words
-static_assert(W_NR == 8 && W_RSTEP == 64, "staging layout: 4 A words, then 4 B words");
 
-__device__ __forceinline__ void w_load(const char* const (&src)[W_NR], int c, u4_t (&set)[W_NR]) {
+// Wave layout of the tile: 4 waves (2 x 2, each 128 x 128) or 8 waves (2 x 4,
+// each 128 x 64, two waves per SIMD).
+template <int WAVES>
+struct WL {
+    static_assert(WAVES == 4 || WAVES == 8, "4 or 8 waves");
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int WAVES_N = WAVES / 2;                   // wave columns
+    static constexpr int WN = W_BN / 32 / WAVES_N;              // 32x32 blocks per wave, columns
+    static constexpr int NR = (W_BM + W_BN) * W_QW / THREADS;   // staged words per thread and chunk
+    static constexpr int RSTEP = THREADS / W_QW;                // rows between a thread's staged words
+};
+
+template <int NR>
+__device__ __forceinline__ void w_load(const char* const (&src)[NR], int c, u4_t (&set)[NR]) {
 #pragma unroll
-    for (int r = 0; r < W_NR; ++r) set[r] = *reinterpret_cast<const u4_t*>(src[r] + c * (W_KC * 2));
+    for (int r = 0; r < NR; ++r) set[r] = *reinterpret_cast<const u4_t*>(src[r] + c * (W_KC * 2));
 }
 
-__device__ __forceinline__ void w_store(char* dst, const u4_t (&set)[W_NR]) {
+template <int NR, int RSTEP>
+__device__ __forceinline__ void w_store(char* dst, const u4_t (&set)[NR]) {
 #pragma unroll
-    for (int r = 0; r < W_NR; ++r) *reinterpret_cast<u4_t*>(dst + r * W_RSTEP * W_ROWB) = set[r];
+    for (int r = 0; r < NR; ++r) *reinterpret_cast<u4_t*>(dst + r * RSTEP * W_ROWB) = set[r];
 }
 
 // Fragments of K-step s (16 elements) of the chunk held in stage `st`.
+template <int WN>
 __device__ __forceinline__ void w_frags(const char* st, int wr, int wc, int lane, int s, u4_t (&fa)[W_WM],
-                                        u4_t (&fb)[W_WN]) {
+                                        u4_t (&fb)[WN]) {
     const int off = (s * 16 + (lane >> 5) * 8) * 2;
     const char* pa = st + (wr * 128 + (lane & 31)) * W_ROWB + off;
-    const char* pb = st + (W_BM + wc * 128 + (lane & 31)) * W_ROWB + off;
+    const char* pb = st + (W_BM + wc * 32 * WN + (lane & 31)) * W_ROWB + off;
 #pragma unroll
     for (int i = 0; i < W_WM; ++i) fa[i] = *reinterpret_cast<const u4_t*>(pa + i * 32 * W_ROWB);
 #pragma unroll
-    for (int j = 0; j < W_WN; ++j) fb[j] = *reinterpret_cast<const u4_t*>(pb + j * 32 * W_ROWB);
+    for (int j = 0; j < WN; ++j) fb[j] = *reinterpret_cast<const u4_t*>(pb + j * 32 * W_ROWB);
 }
 
 // Instruction order of one chunk, for the scheduler: each of the 32 MFMAs
@@ -435,33 +450,35 @@ __device__ __forceinline__ void w_frags(const char* st, int wr, int wc, int lane
 // the LDS copy of a later chunk, its global loads), so the matrix pipe
 // is never left idle while a block of memory instructions issues (one wave
 // per SIMD: no other wave fills the gaps).
+template <int WN, int NW>
 __device__ __forceinline__ void w_schedule() {
     constexpr int MFMA = 0x008, DS_READ = 0x100, DS_WRITE = 0x200, VMEM_READ = 0x020;
+    constexpr int NM = 2 * W_WM * WN, NR = W_WM + WN;  // per chunk: MFMAs, reads per K-step
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NR; ++k) {
         __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
         __builtin_amdgcn_sched_group_barrier(DS_READ, 1, 0);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NW; ++k) {
         __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
         __builtin_amdgcn_sched_group_barrier(DS_WRITE, 1, 0);
         __builtin_amdgcn_sched_group_barrier(VMEM_READ, 1, 0);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NR; ++k) {
         __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
         __builtin_amdgcn_sched_group_barrier(DS_READ, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(MFMA, 8, 0);
+    if constexpr (NM > 2 * NR + NW) __builtin_amdgcn_sched_group_barrier(MFMA, NM - 2 * NR - NW, 0);
 }
 
-template <int PREC>
-__device__ __forceinline__ void w_mfma(f16_t (&acc)[W_WM][W_WN], const u4_t (&fa)[W_WM], const u4_t (&fb)[W_WN]) {
+template <int PREC, int WN>
+__device__ __forceinline__ void w_mfma(f16_t (&acc)[W_WM][WN], const u4_t (&fa)[W_WM], const u4_t (&fb)[WN]) {
 #pragma unroll
     for (int i = 0; i < W_WM; ++i)
 #pragma unroll
-        for (int j = 0; j < W_WN; ++j) {
+        for (int j = 0; j < WN; ++j) {
             if constexpr (PREC == CORR_PREC_BF16)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8_t, fa[i]),
                                                                      __builtin_bit_cast(b8_t, fb[j]), acc[i][j], 0, 0, 0);
@@ -471,12 +488,13 @@ __device__ __forceinline__ void w_mfma(f16_t (&acc)[W_WM][W_WN], const u4_t (&fa
         }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g, int n_ti, int n_tj) {
+template <int PREC, int WAVES>
+__global__ __launch_bounds__(WL<WAVES>::THREADS, 1) void gemm_max_wide_kernel(GemmArgs g, int n_ti, int n_tj) {
+    using L = WL<WAVES>;
     static_assert(PREC == CORR_PREC_F16 || PREC == CORR_PREC_BF16, "single-pass 16-bit operands");
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / L::WAVES_N, wc = wave % L::WAVES_N;  // wave position in the grid
     const int64_t rowb_g = g.K * 2;
     const int n_chunks = (int)(g.K / W_KC);  // a multiple of W_PF: K is a multiple of W_PF * W_KC
     const int last = n_chunks - 1;
@@ -507,30 +525,30 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
         // source rows, clamped to the padded row counts: a 256-row tile may
         // run past buffers padded to 128 rows; rows past na / nb are masked
         // in the epilogue
-        const char* src[W_NR];
+        const char* src[L::NR];
 #pragma unroll
-        for (int r = 0; r < W_NR / 2; ++r) {
-            const int64_t ra = min(row0 + trow + W_RSTEP * r, g.na_pad - 1);
-            const int64_t rb = min(col0 + trow + W_RSTEP * r, g.nb_pad - 1);
+        for (int r = 0; r < L::NR / 2; ++r) {
+            const int64_t ra = min(row0 + trow + L::RSTEP * r, g.na_pad - 1);
+            const int64_t rb = min(col0 + trow + L::RSTEP * r, g.nb_pad - 1);
             src[r] = (const char*)g.a_hi + ra * rowb_g + (tid % W_QW) * 16;
-            src[W_NR / 2 + r] = (const char*)g.b_hi + rb * rowb_g + (tid % W_QW) * 16;
+            src[L::NR / 2 + r] = (const char*)g.b_hi + rb * rowb_g + (tid % W_QW) * 16;
         }
 
-        u4_t set0[W_NR], set1[W_NR];
+        u4_t set0[L::NR], set1[L::NR];
         w_load(src, 0, set0);
         w_load(src, min(1, last), set1);
-        w_store(dst0, set0);
+        w_store<L::NR, L::RSTEP>(dst0, set0);
         w_load(src, min(2, last), set0);
-        w_store(dst0 + W_STAGE, set1);
+        w_store<L::NR, L::RSTEP>(dst0 + W_STAGE, set1);
         w_load(src, min(3, last), set1);
         __syncthreads();
 
-        f16_t acc[W_WM][W_WN];
+        f16_t acc[W_WM][L::WN];
 #pragma unroll
         for (int i = 0; i < W_WM; ++i)
 #pragma unroll
-            for (int j = 0; j < W_WN; ++j) acc[i][j] = f16_t{};
-        u4_t fa0[W_WM], fb0[W_WN], fa1[W_WM], fb1[W_WN];
+            for (int j = 0; j < L::WN; ++j) acc[i][j] = f16_t{};
+        u4_t fa0[W_WM], fb0[L::WN], fa1[W_WM], fb1[L::WN];
         w_frags(smem, wr, wc, lane, 0, fa0, fb0);
 
         // chunk cc in stage st; `set` holds chunk cc + 2 and then takes
@@ -545,11 +563,11 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
         const int sw = sn == W_NST - 1 ? 0 : sn + 1;                            \
         w_frags(smem + st * W_STAGE, wr, wc, lane, 1, fa1, fb1);                \
         w_mfma<PREC>(acc, fa0, fb0);                                            \
-        w_store(dst0 + sw * W_STAGE, set);                                      \
+        w_store<L::NR, L::RSTEP>(dst0 + sw * W_STAGE, set);                                 \
         w_load(src, min((cc) + W_PF + 2, last), set);                           \
         w_frags(smem + sn * W_STAGE, wr, wc, lane, 0, fa0, fb0);                \
         w_mfma<PREC>(acc, fa1, fb1);                                            \
-        w_schedule();                                                           \
+        w_schedule<L::WN, L::NR>();                                                \
         __syncthreads();                                                        \
         st = sn;                                                                \
     }
@@ -559,7 +577,7 @@ __global__ __launch_bounds__(G_THREADS, 1) void gemm_max_wide_kernel(GemmArgs g,
         }
 #undef W_CHUNK
 
-        fold_tile<W_WM, W_WN>(acc, g, row0 + wr * 128, col0 + wc * 128,
+        fold_tile<W_WM, L::WN>(acc, g, row0 + wr * 128, col0 + wc * 32 * L::WN,
                               (row0 + W_BM > g.na) || (col0 + W_BN > g.nb), lane, best, best_key);
     }
     if (lane == 0 && best >= 0.0f) atomicMax(g.key, best_key);
@@ -581,15 +599,15 @@ static int launch_p(const GemmArgs& g, int num_cus, hipStream_t s) {
     return CORR_OK;
 }
 
-template <int PREC>
+template <int PREC, int WAVES>
 static int launch_wide(const GemmArgs& g, int64_t n_ti, int64_t n_tj, int num_cus, hipStream_t s) {
     const int64_t n_tiles = n_ti * n_tj;
     const int grid = (int)(n_tiles < num_cus ? n_tiles : num_cus);
     const size_t lds = (size_t)W_NST * W_STAGE;
     if (g.K <= 0 || g.K % (W_PF * W_KC)) return fail(CORR_EINVAL, "contraction: K not a multiple of the chunk group");
-    int rc = kernel_setup((const void*)gemm_max_wide_kernel<PREC>, lds, G_THREADS, nullptr);
+    int rc = kernel_setup((const void*)gemm_max_wide_kernel<PREC, WAVES>, lds, WL<WAVES>::THREADS, nullptr);
     if (rc) return rc;
-    gemm_max_wide_kernel<PREC><<<dim3((unsigned)grid), G_THREADS, lds, s>>>(g, (int)n_ti, (int)n_tj);
+    gemm_max_wide_kernel<PREC, WAVES><<<dim3((unsigned)grid), WL<WAVES>::THREADS, lds, s>>>(g, (int)n_ti, (int)n_tj);
     CORR_LAUNCH_CHECK();
     return CORR_OK;
 }
@@ -606,9 +624,16 @@ static bool use_wide(const GemmArgs& g, int num_cus, int64_t& n_ti, int64_t& n_t
 int launch_gemm_max(const GemmArgs& g, int num_cus, hipStream_t s) {
     if (g.na == 0 || g.nb == 0) return CORR_OK;
     int64_t n_ti = 0, n_tj = 0;
-    if (use_wide(g, num_cus, n_ti, n_tj))
-        return g.prec == CORR_PREC_F16 ? launch_wide<CORR_PREC_F16>(g, n_ti, n_tj, num_cus, s)
-                                       : launch_wide<CORR_PREC_BF16>(g, n_ti, n_tj, num_cus, s);
+    if (use_wide(g, num_cus, n_ti, n_tj)) {
+        // one tile per CU: 4 waves (its start and epilogue are cheaper);
+        // two or more: 8 waves, two per SIMD, which hide each other's waits
+        const bool eight = n_ti * n_tj >= 2 * (int64_t)num_cus;
+        if (g.prec == CORR_PREC_F16)
+            return eight ? launch_wide<CORR_PREC_F16, 8>(g, n_ti, n_tj, num_cus, s)
+                         : launch_wide<CORR_PREC_F16, 4>(g, n_ti, n_tj, num_cus, s);
+        return eight ? launch_wide<CORR_PREC_BF16, 8>(g, n_ti, n_tj, num_cus, s)
+                     : launch_wide<CORR_PREC_BF16, 4>(g, n_ti, n_tj, num_cus, s);
+    }
     switch (g.prec) {
         case CORR_PREC_F32: return launch_p<CORR_PREC_F32>(g, num_cus, s);
         case CORR_PREC_F16: return launch_p<CORR_PREC_F16>(g, num_cus, s);

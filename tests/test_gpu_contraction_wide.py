@@ -110,3 +110,60 @@ def test_wide_tiles_planted_pairs(env, prec):
         assert (int(got["pa"]), int(got["pb"])) == (pa, pb)
         assert abs(got["value"] - abs(r)) <= TOL[prec]
         assert abs(got["signed_value"] - r) <= TOL[prec]
+
+
+# Bricks of 6000 x 6300 points: 24 x 25 = 600 tiles, at least two per CU, so
+# the eight-wave layout runs (2 x 4 waves of 128 x 64); ragged against the
+# 256-row tiles and the 128-row padding.
+DIMS8 = (50, 40, 8)
+RA8 = (0, 0, 0, 25, 40, 6)
+RB8 = (25, 0, 0, 25, 36, 7)
+
+
+def _indices8(r):
+    return synth.Region(*r).global_indices(DIMS8[0], DIMS8[1])
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+@pytest.mark.parametrize("M", [129, 300])
+def test_eight_wave_tiles_against_oracle(env, M, prec):
+    pc, ctx, torch = env["pc"], env["ctx"], env["torch"]
+    rng = np.random.default_rng(100 + M)
+    P = DIMS8[0] * DIMS8[1] * DIMS8[2]
+    common = rng.standard_normal((M, 4))
+    mix = rng.standard_normal((4, P)) * (rng.uniform(size=P) < 0.3)
+    data = np.ascontiguousarray((rng.standard_normal((M, P)) + common @ mix).astype(np.float32))
+    f = pc.Field(torch.from_numpy(data).cuda(), *DIMS8)
+    got = ctx.corr_region_max(f, pc.region(*RA8), pc.region(*RB8), "pearson", prec)
+    ia, ib = _indices8(RA8), _indices8(RB8)
+    ref = oracle.pearson_region_max_matmul(data, ia, ib)
+    _say(f"  eight-wave M={M} {prec}: gpu {got['value']:.6f} oracle {ref['value']:.6f}")
+    assert abs(got["value"] - ref["value"]) <= TOL[prec]
+    assert got["n_evaluated"] == ref["n_evaluated"]
+    check_pearson_argmax(got, ref, data, ia, ib, TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_eight_wave_tiles_planted_pairs(env, prec):
+    pc, ctx, torch = env["pc"], env["ctx"], env["torch"]
+    M = 160
+    rng = np.random.default_rng(6)
+    base = rng.standard_normal((M, DIMS8[0] * DIMS8[1] * DIMS8[2])).astype(np.float32)
+    ia, ib = _indices8(RA8), _indices8(RB8)
+    # every wave (2 rows x 4 columns of 128 x 64) and accumulator block of a
+    # tile, the first / last rows and columns, the ragged edge tiles
+    pos = [(0, 0), (5999, 6299), (5888, 6144), (5999, 0), (0, 6299)]
+    for wr in range(2):
+        for wc in range(4):
+            for i in range(4):
+                pos.append((256 * 3 + wr * 128 + i * 32 + (7 * i + 5) % 32, 256 * 5 + wc * 64 + (i % 2) * 32 + (3 * i + 9) % 32))
+    for la, lb in pos:
+        pa, pb = int(ia[la]), int(ib[lb])
+        data = base.copy()
+        data[:, pb] = 0.98 * data[:, pa] + 0.2 * rng.standard_normal(M).astype(np.float32)
+        f = pc.Field(torch.from_numpy(data).cuda(), *DIMS8)
+        got = ctx.corr_region_max(f, pc.region(*RA8), pc.region(*RB8), "pearson", prec)
+        r = float(oracle.pearson_pairs(data, np.array([[pa, pb]], np.int32))[0])
+        assert (int(got["pa"]), int(got["pb"])) == (pa, pb), ((la, lb), got)
+        assert abs(got["value"] - abs(r)) <= TOL[prec]
+        assert abs(got["signed_value"] - r) <= TOL[prec]
