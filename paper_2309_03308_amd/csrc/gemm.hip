@@ -28,7 +28,8 @@
 //    order;
 //  - single-pass 16-bit operands on bricks large enough to give every CU a
 //    256 x 256 tile take the wide-tile kernel further down (one workgroup
-//    per CU, 128 x 128 per wave).
+//    per CU: 4 waves of 128 x 128 at one tile per CU, 8 waves of 128 x 64
+//    from two tiles per CU on).
 #include "common.h"
 
 namespace corr {
